@@ -1,0 +1,158 @@
+"""Oracle: TEST INFRASTRUCTURE ONLY.
+
+A plain, sequential CPU implementation of the paper's four-step parallel
+samplesort with exact splitting (PSES; arXiv 2305.05245, Section 2, Section 2.3
+Eq. 1 and Eq. 2), written in C (``pses_oracle.c``) and wrapped here with ctypes
+and numpy.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
+of ``bench.py`` may import this package; the GPU library never does.
+
+Everything here works on raw key bits: floats are compared by IEEE totalOrder
+written out from its definition, never by a floating-point compare.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pses_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+# key-type codes of the oracle (same numbering as the public library's enum)
+DTYPES = {
+    "u32": (0, np.uint32),
+    "i32": (1, np.int32),
+    "u64": (2, np.uint64),
+    "i64": (3, np.int64),
+    "f32": (4, np.float32),
+    "f64": (5, np.float64),
+}
+BITS_VIEW = {4: np.uint32, 8: np.uint64}
+
+ERRORS = {
+    1: "bad arguments",
+    2: "out of memory",
+    10: "Eq. 1 violated",
+    11: "c_k out of range",
+    12: "sum of split positions != r_k",
+    13: "split positions not monotone",
+    14: "offset O_k != r_k",
+    15: "partition size not floor/ceil(N/n_P)",
+    16: "no pivot candidate",
+}
+
+
+def build(force: bool = False) -> str:
+    """Compile pses_oracle.c with gcc into liboracle.so (next to the source)."""
+    with _lock:
+        if force or not os.path.exists(_LIB_PATH) or (
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)
+        ):
+            tmp = _LIB_PATH + f".tmp{os.getpid()}"
+            subprocess.check_call(
+                ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+                 "-o", tmp, _SRC]
+            )
+            os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def bind(path: str):
+    """ctypes handle for a compiled oracle at `path` (the default build, or a
+    mutated copy compiled by the tests that check the pins catch mistakes)."""
+    lib = ctypes.CDLL(path)
+    u64, u32, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p
+    lib.oracle_compare.argtypes = [ctypes.c_int, u64, u64]
+    lib.oracle_compare.restype = ctypes.c_int
+    lib.oracle_pses.argtypes = [ctypes.c_int, u64, vp, vp, u32, u32, vp, vp,
+                                vp, vp, vp, vp, vp, ctypes.c_int]
+    lib.oracle_pses.restype = ctypes.c_int
+    lib.oracle_rank_counts.argtypes = [ctypes.c_int, u64, vp, u64, vp, vp]
+    lib.oracle_rank_counts.restype = None
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = bind(_LIB_PATH)
+    return _lib
+
+
+def dtype_code(dtype: str) -> int:
+    return DTYPES[dtype][0]
+
+
+def to_bits(x) -> int:
+    """Raw bits of one numpy scalar as a Python int (zero-extended)."""
+    a = np.asarray(x)
+    return int(a.view(BITS_VIEW[a.dtype.itemsize]))
+
+
+def compare(dtype: str, a_bits: int, b_bits: int, lib=None) -> int:
+    """Step O0: -1, 0, +1 for the key order of `dtype` on raw bits."""
+    return int((lib or _load()).oracle_compare(dtype_code(dtype), a_bits, b_bits))
+
+
+@dataclass
+class PsesResult:
+    keys: np.ndarray          # sorted output
+    vals: np.ndarray | None   # payload in output order (stable by input index)
+    blocks: np.ndarray        # step 1: concatenation of the sorted blocks
+    pivots: np.ndarray        # step 2: canonical P_1..P_{n_P-1} (raw key dtype)
+    counts: np.ndarray        # step 2: c_1..c_{n_P-1} (uint64)
+    split: np.ndarray         # step 3: [n_B, n_P+1] uint64 boundaries
+    offsets: np.ndarray       # step 4: O_0..O_{n_P} (uint64)
+
+
+def pses(keys: np.ndarray, n_blocks: int, n_parts: int, vals: np.ndarray | None = None,
+         merge_kind: int = 0, lib=None) -> PsesResult:
+    """Run the whole sequential method on host arrays.  Raises on any violated
+    invariant (Eq. 1, Eq. 2 range, split sums, offsets, partition sizes)."""
+    keys = np.ascontiguousarray(keys)
+    name = {np.dtype(v[1]): k for k, v in DTYPES.items()}[keys.dtype]
+    code = dtype_code(name)
+    n = keys.size
+    out = np.empty_like(keys)
+    blocks = np.empty_like(keys)
+    pivots = np.zeros(max(n_parts - 1, 0), dtype=keys.dtype)
+    counts = np.zeros(max(n_parts - 1, 0), dtype=np.uint64)
+    split = np.zeros((n_blocks, n_parts + 1), dtype=np.uint64)
+    offsets = np.zeros(n_parts + 1, dtype=np.uint64)
+    vin = vout = None
+    if vals is not None:
+        vin = np.ascontiguousarray(vals, dtype=np.uint32)
+        assert vin.size == n
+        vout = np.empty_like(vin)
+
+    def p(a):
+        return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+    rc = (lib or _load()).oracle_pses(code, n, p(keys), p(vin), n_blocks, n_parts, p(out), p(vout),
+                             p(blocks), p(pivots) if pivots.size else None,
+                             p(counts) if counts.size else None, p(split), p(offsets),
+                             merge_kind)
+    if rc != 0:
+        raise RuntimeError(f"oracle_pses failed: {ERRORS.get(rc, rc)}")
+    return PsesResult(out, vout, blocks, pivots, counts, split, offsets)
+
+
+def rank_counts(keys: np.ndarray, v, lib=None) -> tuple[int, int]:
+    """|{x < v}| and |{x <= v}| over `keys` by a linear pass (Eq. 1's counts)."""
+    keys = np.ascontiguousarray(keys)
+    name = {np.dtype(t[1]): k for k, t in DTYPES.items()}[keys.dtype]
+    lt = ctypes.c_uint64()
+    le = ctypes.c_uint64()
+    (lib or _load()).oracle_rank_counts(dtype_code(name), keys.size,
+                               keys.ctypes.data_as(ctypes.c_void_p),
+                               to_bits(np.asarray(v, dtype=keys.dtype)),
+                               ctypes.byref(lt), ctypes.byref(le))
+    return int(lt.value), int(le.value)

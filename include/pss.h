@@ -1,0 +1,174 @@
+/*
+ * pss.h -- C ABI of libpss: parallel samplesort with exact splitting (PSES)
+ * on AMD MI355X (gfx950).
+ *
+ * The library sorts N keys ascending into a separate output array, following
+ * the problem statement of Tokuue & Ishiyama, "Performance Evaluation of
+ * Parallel Sortings on the Supercomputer Fugaku" (arXiv 2305.05245), Section 2:
+ * the input A is cut into n_B contiguous blocks of length ceil(N/n_B), each
+ * block is sorted (step 1), n_P - 1 pivots P_1..P_{n_P-1} are chosen with the
+ * implicit sentinels P_0 = -inf and P_{n_P} = +inf (step 2), every sorted block
+ * is cut into n_P partitions (step 3), and the k-th partitions of all blocks
+ * are merged into the output at an offset that is the sum of the sizes of the
+ * partitions before it (step 4).  Pivots are chosen by exact splitting
+ * (Section 2.3, Eq. 1 and Eq. 2): with r_k = floor(k N / n_P),
+ *     |{x < P_k}| <= r_k <= |{x <= P_k}|  and  c_k = r_k - |{x < P_k}|,
+ * so every partition holds floor(N/n_P) or ceil(N/n_P) keys however many keys
+ * are equal.  Of the keys equal to P_k, the c_k that go left are taken from the
+ * lowest-numbered block first, earliest position first.
+ *
+ * Conventions for every call:
+ *  - Pointers named *_in, *_out, ws, pivots, counts, split, offsets are DEVICE
+ *    pointers (memory owned by the caller, e.g. torch tensors).  Host pointers
+ *    are only the out-parameters of pss_create, pss_workspace_bytes,
+ *    pss_plan_describe and pss_validate's arguments, which are never
+ *    dereferenced.
+ *  - Every call that launches work is asynchronous on `stream` (a hipStream_t
+ *    passed as void*, NULL = the null stream) and returns once the work is
+ *    queued.  The caller synchronises.
+ *  - keys_in is never written.  Input and output must not overlap (the method
+ *    is out of place: the output needs its own N elements, Section 4).
+ *  - Errors are returned as status codes; nothing is thrown across the ABI.
+ *    pss_last_error() gives a message for the last failing call on a context
+ *    (or on the calling thread when the context is NULL).
+ *  - A context is used by one host thread at a time.
+ *  - Key order: unsigned/signed integers by value; float32/float64 by IEEE
+ *    754-2019 totalOrder (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN),
+ *    so the output is unique bit for bit.  Key-value sorts are stable: equal
+ *    keys keep their input order.
+ */
+#ifndef PSS_H
+#define PSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PSS_U32 = 0,
+  PSS_I32 = 1,
+  PSS_U64 = 2,
+  PSS_I64 = 3,
+  PSS_F32 = 4, /* IEEE totalOrder */
+  PSS_F64 = 5  /* IEEE totalOrder */
+} pss_key_t;
+
+typedef enum {
+  PSS_VAL_NONE = 0, /* keys only */
+  PSS_VAL_U32 = 1   /* one uint32 payload per key, stable by input index */
+} pss_val_t;
+
+typedef enum {
+  PSS_OK = 0,
+  PSS_ERR_INVALID = 1,     /* bad argument (null pointer, overlap, bad enum)  */
+  PSS_ERR_UNSUPPORTED = 2, /* valid request outside this build's limits       */
+  PSS_ERR_OOM = 3,         /* host allocation failed                          */
+  PSS_ERR_HIP = 4,         /* a HIP runtime call failed (see pss_last_error)  */
+  PSS_ERR_WORKSPACE = 5    /* workspace missing or smaller than required      */
+} pss_status;
+
+typedef struct pss_ctx pss_ctx;
+
+/* Limits of this build. */
+#define PSS_MAX_KEYS ((uint64_t)2147483647u) /* n < 2^31                      */
+#define PSS_MAX_BLOCKS 2048u                 /* explicit n_B                  */
+#define PSS_MAX_PARTS 4194304u               /* explicit n_P                  */
+
+/* Create a context bound to HIP device `device`.  Returns PSS_ERR_HIP when the
+ * device does not exist.  *out receives the handle (NULL on failure). */
+pss_status pss_create(int device, pss_ctx **out);
+
+/* Destroy a context (NULL is allowed).  Pending work is not waited for. */
+void pss_destroy(pss_ctx *ctx);
+
+/* Static English name of a status code. */
+const char *pss_status_string(pss_status s);
+
+/* Message of the last failing call on ctx (or on this thread if ctx is NULL);
+ * "" if none.  Valid until the next call on the same context or thread. */
+const char *pss_last_error(const pss_ctx *ctx);
+
+/* Argument check performed by pss_sort before anything touches the device;
+ * exposed so it can be exercised without a GPU.  keys_in/keys_out/vals_* are
+ * compared as addresses only.  Returns PSS_OK, PSS_ERR_INVALID,
+ * PSS_ERR_UNSUPPORTED or PSS_ERR_WORKSPACE (ws_bytes below the requirement;
+ * pass SIZE_MAX to skip that check). */
+pss_status pss_validate(pss_key_t key, pss_val_t val, const void *keys_in, const void *keys_out,
+                        const void *vals_in, const void *vals_out, uint64_t n,
+                        uint32_t n_blocks, uint32_t n_parts, size_t ws_bytes);
+
+/* Device workspace pss_sort / pss_splitters need for these arguments (bytes,
+ * 256-byte aligned pieces).  Host-only arithmetic; ctx may be NULL. */
+pss_status pss_workspace_bytes(const pss_ctx *ctx, pss_key_t key, pss_val_t val, uint64_t n,
+                               uint32_t n_blocks, uint32_t n_parts, size_t *bytes);
+
+/* Plan of the launches pss_sort makes for these arguments, as a
+ * NUL-terminated JSON object written to buf (host memory of buf_len bytes):
+ *   {"mode": "auto"|"paper", "tile": T, "part": T_m, "passes": [fan-in, ...],
+ *    "block_passes": [...], "n_blocks": n_B, "n_parts": n_P, "hbm_passes": h}
+ * where "passes" are the merge passes after the tile sort and "hbm_passes"
+ * the number of full read+write sweeps over the keys.  Host-only. */
+pss_status pss_plan_describe(pss_key_t key, pss_val_t val, uint64_t n, uint32_t n_blocks,
+                             uint32_t n_parts, char *buf, size_t buf_len);
+
+/*
+ * Sort n keys (and, with PSS_VAL_U32, their uint32 payloads) ascending.
+ *
+ *   n_blocks = n_parts = 0: automatic plan.  The input is cut into LDS-sized
+ *     blocks (tiles); step 1 sorts each tile; steps 2-4 are then applied level
+ *     by level, each level merging groups of sorted runs with exact splitting
+ *     into LDS-sized partitions, until one run remains.
+ *   n_blocks > 0 and n_parts > 0: the paper's single-level method with those
+ *     n_B and n_P: n_B blocks of ceil(N/n_B) keys are sorted, exact splitters
+ *     P_1..P_{n_P-1} cut every block, and partition k of all blocks is merged
+ *     to output offset O_k = sum of the sizes of partitions 0..k-1 (computed on
+ *     the device by an exclusive scan).  A partition larger than one LDS-sized
+ *     merge is merged in chunks cut at exact ranks inside it.
+ *   Exactly one of n_blocks, n_parts zero: PSS_ERR_INVALID.
+ *
+ * keys_in: n keys of the given type, never written.  keys_out: n keys.
+ * vals_in/vals_out: n uint32 each when val == PSS_VAL_U32 (ignored otherwise).
+ * ws: device workspace of at least pss_workspace_bytes(...) bytes, owned by
+ * the caller; its contents are scratch and may be left changed.
+ * n == 0 is a no-op.  Returns PSS_OK once all launches are queued.
+ */
+pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys_in,
+                    void *keys_out, const uint32_t *vals_in, uint32_t *vals_out, uint64_t n,
+                    uint32_t n_blocks, uint32_t n_parts, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/*
+ * Steps 1-3 of the paper's method with explicit n_B, n_P (n_blocks, n_parts
+ * > 0), for inspection and parity checks.  Any output may be NULL.
+ *   sorted_blocks: n keys, the concatenation of the sorted blocks (step 1).
+ *   pivots: n_P - 1 keys, P_k = the key of rank r_k - 1 (the smallest key v
+ *     with |{x <= v}| >= r_k, one valid choice under Eq. 1); 0 when r_k = 0.
+ *   counts: n_P - 1 values c_k of Eq. 2 (0 when r_k = 0).
+ *   split: n_B * (n_P + 1) values, row-major [b][k]: partition k of sorted
+ *     block b is [split[b][k], split[b][k+1]) (step 3).
+ *   offsets: n_P + 1 values O_k (O_0 = 0, O_{n_P} = n), from the device scan.
+ * Workspace as for pss_sort with the same n_blocks, n_parts.
+ */
+pss_status pss_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, uint64_t n,
+                         uint32_t n_blocks, uint32_t n_parts, void *sorted_blocks, void *pivots,
+                         uint64_t *counts, uint64_t *split, uint64_t *offsets, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/*
+ * Wait for all work on ctx's device, then read and clear the library's device
+ * error word into *code (host memory): 0 when every kernel found its
+ * invariants intact.  Bits: 1 = splitter candidate set overflow, 2 = splitter
+ * target outside its bracket, 4 = split position outside its run, 8 = merged
+ * segments do not add up to their partition.  A kernel that sets a bit stops
+ * before writing outside its own partition, and its output is then invalid.
+ * Meant for tests and debugging; it synchronises the whole device.
+ */
+pss_status pss_device_check(pss_ctx *ctx, uint32_t *code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSS_H */

@@ -1,0 +1,146 @@
+"""pss: parallel samplesort with exact splitting (PSES) for AMD MI355X.
+
+Python face of libpss (include/pss.h).  PyTorch supplies device memory and the
+current HIP stream; every step of the sort runs in the library's HIP kernels.
+
+    import paper_2305_05245_amd as pss
+    out, _ = pss.sort(keys)                      # automatic multi-level plan
+    out, vals = pss.sort(keys, vals)             # stable key-value sort
+    out, _ = pss.sort(keys, n_blocks=64, n_parts=64)   # the paper's single level
+    info = pss.splitters(keys, 64, 64)           # steps 1-3 (pivots, c_k, split)
+"""
+from __future__ import annotations
+
+import threading
+
+import torch
+
+from . import _lib
+from ._lib import PssError, plan, validate, workspace_bytes  # noqa: F401
+
+__all__ = ["sort", "splitters", "device_check", "key_type_of", "plan", "workspace_bytes", "PssError",
+           "Workspace"]
+
+_DTYPE_KEY = {
+    torch.int32: _lib.I32,
+    torch.int64: _lib.I64,
+    torch.float32: _lib.F32,
+    torch.float64: _lib.F64,
+}
+for _name, _code in (("uint32", _lib.U32), ("uint64", _lib.U64)):
+    if hasattr(torch, _name):
+        _DTYPE_KEY[getattr(torch, _name)] = _code
+
+_ctx_lock = threading.Lock()
+_contexts: dict[int, _lib.Context] = {}
+
+
+def _context(device: int) -> _lib.Context:
+    with _ctx_lock:
+        c = _contexts.get(device)
+        if c is None:
+            c = _lib.Context(device)
+            _contexts[device] = c
+        return c
+
+
+class Workspace:
+    """Grow-only device scratch buffer, one per device (caller-owned memory
+    handed to the library as `ws`)."""
+
+    _per_device: dict[int, "Workspace"] = {}
+
+    def __init__(self, device: int):
+        self.device = device
+        self.buf = torch.empty(0, dtype=torch.uint8, device=f"cuda:{device}")
+
+    @classmethod
+    def get(cls, device: int, nbytes: int) -> torch.Tensor:
+        ws = cls._per_device.get(device)
+        if ws is None:
+            ws = cls._per_device[device] = cls(device)
+        if ws.buf.numel() < nbytes:
+            ws.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{device}")
+        return ws.buf
+
+
+def key_type_of(t: torch.Tensor, key_type: str | int | None = None) -> int:
+    if key_type is not None:
+        return _lib.KEY_NAMES[key_type] if isinstance(key_type, str) else int(key_type)
+    try:
+        return _DTYPE_KEY[t.dtype]
+    except KeyError:
+        raise TypeError(f"unsupported key dtype {t.dtype}") from None
+
+
+def _stream_handle(device: int) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def sort(keys: torch.Tensor, vals: torch.Tensor | None = None, n_blocks: int = 0,
+         n_parts: int = 0, key_type: str | int | None = None, out: torch.Tensor | None = None,
+         vals_out: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    """Sort a 1-D device tensor ascending (floats by IEEE totalOrder); with
+    `vals` (uint32 payload, any 4-byte dtype) the sort is stable.  Returns
+    (sorted_keys, sorted_vals or None).  Asynchronous on the current stream."""
+    if not keys.is_cuda or keys.dim() != 1 or not keys.is_contiguous():
+        raise ValueError("keys must be a contiguous 1-D device tensor")
+    kt = key_type_of(keys, key_type)
+    if keys.element_size() != _lib.KEY_BYTES[kt]:
+        raise ValueError("key dtype width does not match key_type")
+    dev = keys.device.index if keys.device.index is not None else torch.cuda.current_device()
+    n = keys.numel()
+    vt = _lib.VAL_NONE
+    if vals is not None:
+        if not vals.is_cuda or vals.numel() != n or vals.element_size() != 4 or not vals.is_contiguous():
+            raise ValueError("vals must be a contiguous device tensor of n 4-byte elements")
+        vt = _lib.VAL_U32
+    if out is None:
+        out = torch.empty_like(keys)
+    if vals is not None and vals_out is None:
+        vals_out = torch.empty_like(vals)
+    need = _lib.workspace_bytes(kt, vt, n, n_blocks, n_parts)
+    ws = workspace if workspace is not None else Workspace.get(dev, need)
+    ctx = _context(dev)
+    ctx.sort(kt, vt, keys.data_ptr(), out.data_ptr(),
+             vals.data_ptr() if vals is not None else 0,
+             vals_out.data_ptr() if vals is not None else 0,
+             n, n_blocks, n_parts, ws.data_ptr(), ws.numel(), _stream_handle(dev))
+    return out, (vals_out if vals is not None else None)
+
+
+def device_check(device: int = 0) -> int:
+    """Synchronise `device` and return (and clear) the library's device error
+    word: 0 when every kernel found its invariants intact."""
+    return _context(device).device_check()
+
+
+def splitters(keys: torch.Tensor, n_blocks: int, n_parts: int,
+              key_type: str | int | None = None) -> dict:
+    """Steps 1-3 of the paper's method on the device: sorted blocks, canonical
+    pivots P_k, counts c_k (Eq. 2), the split table [n_B, n_P+1] and the
+    offsets O_k of the merged partitions."""
+    if not keys.is_cuda or keys.dim() != 1 or not keys.is_contiguous():
+        raise ValueError("keys must be a contiguous 1-D device tensor")
+    kt = key_type_of(keys, key_type)
+    dev = keys.device.index if keys.device.index is not None else torch.cuda.current_device()
+    n = keys.numel()
+    d = keys.device
+    res = {
+        "sorted_blocks": torch.empty_like(keys),
+        "pivots": torch.zeros(max(n_parts - 1, 0), dtype=keys.dtype, device=d),
+        "counts": torch.zeros(max(n_parts - 1, 0), dtype=torch.int64, device=d),
+        "split": torch.zeros((n_blocks, n_parts + 1), dtype=torch.int64, device=d),
+        "offsets": torch.zeros(n_parts + 1, dtype=torch.int64, device=d),
+    }
+    need = _lib.workspace_bytes(kt, _lib.VAL_NONE, n, n_blocks, n_parts)
+    ws = Workspace.get(dev, need)
+    ctx = _context(dev)
+
+    def ptr(t):
+        return t.data_ptr() if t.numel() else 0
+
+    ctx.splitters(kt, keys.data_ptr(), n, n_blocks, n_parts, ptr(res["sorted_blocks"]),
+                  ptr(res["pivots"]), ptr(res["counts"]), ptr(res["split"]), ptr(res["offsets"]),
+                  ws.data_ptr(), ws.numel(), _stream_handle(dev))
+    return res

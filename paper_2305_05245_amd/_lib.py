@@ -1,0 +1,142 @@
+"""ctypes binding of libpss (include/pss.h): argument marshalling only.
+
+Every step of the sort runs in the HIP kernels of libpss.so.  There is no CPU
+fallback: if the library has not been built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpss.so")
+
+# pss_key_t
+U32, I32, U64, I64, F32, F64 = 0, 1, 2, 3, 4, 5
+KEY_NAMES = {"u32": U32, "i32": I32, "u64": U64, "i64": I64, "f32": F32, "f64": F64}
+KEY_BYTES = {U32: 4, I32: 4, U64: 8, I64: 8, F32: 4, F64: 8}
+# pss_val_t
+VAL_NONE, VAL_U32 = 0, 1
+# pss_status
+OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_OOM, ERR_HIP, ERR_WORKSPACE = range(6)
+
+# Names and signatures of every entry point in include/pss.h.
+_c = ctypes
+_vp, _u64, _u32, _sz, _int = _c.c_void_p, _c.c_uint64, _c.c_uint32, _c.c_size_t, _c.c_int
+SIGNATURES = {
+    "pss_create": (_int, [_int, _c.POINTER(_vp)]),
+    "pss_destroy": (None, [_vp]),
+    "pss_status_string": (_c.c_char_p, [_int]),
+    "pss_last_error": (_c.c_char_p, [_vp]),
+    "pss_validate": (_int, [_int, _int, _vp, _vp, _vp, _vp, _u64, _u32, _u32, _sz]),
+    "pss_workspace_bytes": (_int, [_vp, _int, _int, _u64, _u32, _u32, _c.POINTER(_sz)]),
+    "pss_plan_describe": (_int, [_int, _int, _u64, _u32, _u32, _c.c_char_p, _sz]),
+    "pss_sort": (_int, [_vp, _int, _int, _vp, _vp, _vp, _vp, _u64, _u32, _u32, _vp, _sz, _vp]),
+    "pss_device_check": (_int, [_vp, _c.POINTER(_u32)]),
+    "pss_splitters": (_int, [_vp, _int, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
+                             _vp]),
+}
+
+_lock = threading.Lock()
+_lib = None
+
+
+class PssError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_string(status)}: {message}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libpss.so (once).  Raises FileNotFoundError if it is not built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(path):
+                raise FileNotFoundError(
+                    f"{path} is missing: build the HIP library first "
+                    "(python -m paper_2305_05245_amd.build)")
+            lib = ctypes.CDLL(path)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return load().pss_status_string(status).decode()
+
+
+def last_error(ctx=None) -> str:
+    return (load().pss_last_error(ctx) or b"").decode()
+
+
+def check(status: int, ctx=None) -> None:
+    if status != OK:
+        raise PssError(status, last_error(ctx))
+
+
+def validate(key: int, val: int, keys_in: int, keys_out: int, vals_in: int, vals_out: int,
+             n: int, n_blocks: int = 0, n_parts: int = 0, ws_bytes: int | None = None) -> int:
+    """pss_validate: the argument check of pss_sort (no device access)."""
+    ws = ctypes.c_size_t(-1).value if ws_bytes is None else ws_bytes
+    return load().pss_validate(key, val, keys_in or None, keys_out or None, vals_in or None,
+                               vals_out or None, n, n_blocks, n_parts, ws)
+
+
+def workspace_bytes(key: int, val: int, n: int, n_blocks: int = 0, n_parts: int = 0) -> int:
+    out = ctypes.c_size_t()
+    check(load().pss_workspace_bytes(None, key, val, n, n_blocks, n_parts, ctypes.byref(out)))
+    return int(out.value)
+
+
+def plan(key: int, val: int, n: int, n_blocks: int = 0, n_parts: int = 0) -> dict:
+    buf = ctypes.create_string_buffer(4096)
+    check(load().pss_plan_describe(key, val, n, n_blocks, n_parts, buf, len(buf)))
+    return json.loads(buf.value.decode())
+
+
+class Context:
+    """One pss_ctx bound to a HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        check(self.lib.pss_create(device, ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            self.lib.pss_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sort(self, key: int, val: int, keys_in: int, keys_out: int, vals_in: int, vals_out: int,
+             n: int, n_blocks: int, n_parts: int, ws: int, ws_bytes: int, stream: int) -> None:
+        check(self.lib.pss_sort(self.handle, key, val, keys_in or None, keys_out or None,
+                                vals_in or None, vals_out or None, n, n_blocks, n_parts,
+                                ws or None, ws_bytes, stream or None), self.handle)
+
+    def device_check(self) -> int:
+        """Synchronise the device and return (and clear) the error word."""
+        code = ctypes.c_uint32()
+        check(self.lib.pss_device_check(self.handle, ctypes.byref(code)), self.handle)
+        return int(code.value)
+
+    def splitters(self, key: int, keys_in: int, n: int, n_blocks: int, n_parts: int,
+                  sorted_blocks: int, pivots: int, counts: int, split: int, offsets: int,
+                  ws: int, ws_bytes: int, stream: int) -> None:
+        check(self.lib.pss_splitters(self.handle, key, keys_in or None, n, n_blocks, n_parts,
+                                     sorted_blocks or None, pivots or None, counts or None,
+                                     split or None, offsets or None, ws or None, ws_bytes,
+                                     stream or None), self.handle)

@@ -1,0 +1,414 @@
+// C-ABI layer of libpss: argument checks, launch planning, workspace layout
+// and the launch sequence of the sort (see include/pss.h for the contract).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pss.h"
+#include "pss_internal.hpp"
+
+struct pss_ctx {
+  int device = 0;
+  std::string last_error;
+};
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+pss_status fail(const pss_ctx *ctx, pss_status s, const std::string &msg) {
+  if (ctx) const_cast<pss_ctx *>(ctx)->last_error = msg;
+  g_thread_error = msg;
+  return s;
+}
+
+pss_status hip_fail(const pss_ctx *ctx, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return fail(ctx, PSS_ERR_HIP, m);
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Largest table (rows x fan entries of uint32) this build allocates.
+constexpr uint64_t kMaxTableEntries = (uint64_t)1 << 28;
+
+// Merge passes that sort every segment of seg_len keys, starting from sorted
+// tiles of kTile keys: the number of doublings needed is split as evenly as
+// possible over passes of at most 2^kMaxFanLog2 runs each.
+std::vector<pss::RunGeom> plan_segment_passes(uint64_t n, uint64_t seg_len) {
+  std::vector<pss::RunGeom> passes;
+  if (n == 0 || seg_len == 0) return passes;
+  const uint64_t tiles = ceil_div(seg_len, pss::kTile);
+  int bits = 0;
+  while (((uint64_t)1 << bits) < tiles) ++bits;
+  if (bits == 0) return passes;
+  const int npass = (bits + pss::kMaxFanLog2 - 1) / pss::kMaxFanLog2;
+  const uint64_t nseg = ceil_div(n, seg_len);
+  uint64_t run = pss::kTile;
+  for (int q = 0; q < npass; ++q) {
+    const int b = bits / npass + (q < bits % npass ? 1 : 0);
+    pss::RunGeom g{};
+    g.n = n;
+    g.seg_len = seg_len;
+    g.run_len = run;
+    g.fan = 1u << b;
+    g.group_len = std::min<uint64_t>((uint64_t)g.fan * run, seg_len);
+    g.groups_per_seg = ceil_div(seg_len, g.group_len);
+    g.n_groups = nseg * g.groups_per_seg;
+    g.part_len = pss::kPart;
+    g.rows_per_group = (uint32_t)ceil_div(g.group_len, g.part_len) + 1;
+    g.paper = 0;
+    passes.push_back(g);
+    run = std::min<uint64_t>((uint64_t)g.fan * run, seg_len);
+  }
+  return passes;
+}
+
+struct Plan {
+  bool paper = false;
+  bool kv = false;
+  int kb = 8;
+  uint64_t n = 0;
+  uint64_t seg_len = 0;               // segment sorted by tile sort + passes
+  std::vector<pss::RunGeom> passes;   // merge passes inside each segment
+  pss::RunGeom top{};                 // paper mode: the cross-block merge
+  uint64_t table_entries = 0;
+  // workspace layout (byte offsets)
+  size_t off_keys0 = 0, off_keys1 = 0, off_vals0 = 0, off_vals1 = 0;
+  size_t off_table = 0, off_sizes = 0, off_offsets = 0, total = 0;
+};
+
+pss_status make_plan(pss_key_t key, pss_val_t val, uint64_t n, uint32_t n_blocks,
+                     uint32_t n_parts, Plan *p, std::string *err) {
+  p->kv = val == PSS_VAL_U32;
+  p->kb = pss::key_bytes((int)key);
+  p->n = n;
+  p->paper = n_blocks > 0;
+  if (!p->paper) {
+    p->seg_len = n;
+    p->passes = plan_segment_passes(n, n);
+  } else {
+    const uint64_t L = n ? ceil_div(n, n_blocks) : 0;
+    p->seg_len = L;
+    p->passes = plan_segment_passes(n, L);
+    pss::RunGeom &t = p->top;
+    t.n = n;
+    t.seg_len = n;
+    t.run_len = L ? L : 1;
+    t.fan = n_blocks;
+    t.group_len = n;
+    t.groups_per_seg = 1;
+    t.n_groups = 1;
+    t.part_len = pss::kPart;
+    t.paper = 1;
+    t.n_parts = n_parts;
+    t.sub_per_part = (uint32_t)std::max<uint64_t>(1, ceil_div(ceil_div(n, n_parts), pss::kPart));
+    t.rows_per_group = 0;
+    const uint64_t entries = t.total_rows() * (uint64_t)t.fan;
+    if (entries > kMaxTableEntries) {
+      *err = "n_blocks * n_parts too large for the split table of this build";
+      return PSS_ERR_UNSUPPORTED;
+    }
+    p->table_entries = entries;
+  }
+  for (const auto &g : p->passes)
+    p->table_entries = std::max<uint64_t>(p->table_entries, g.total_rows() * (uint64_t)g.fan);
+
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  p->off_keys0 = take(n * (size_t)p->kb);
+  p->off_keys1 = p->paper ? take(n * (size_t)p->kb) : 0;
+  if (p->kv) {
+    p->off_vals0 = take(n * sizeof(uint32_t));
+    p->off_vals1 = p->paper ? take(n * sizeof(uint32_t)) : 0;
+  }
+  p->off_table = take(p->table_entries * sizeof(uint32_t));
+  if (p->paper) {
+    p->off_sizes = take((size_t)n_parts * sizeof(uint64_t));
+    p->off_offsets = take(((size_t)n_parts + 1) * sizeof(uint64_t));
+  }
+  p->total = off;
+  return PSS_OK;
+}
+
+bool overlaps(const void *a, size_t alen, const void *b, size_t blen) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return alen && blen && x < y + blen && y < x + alen;
+}
+
+pss_status validate(const pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys_in,
+                    const void *keys_out, const void *vals_in, const void *vals_out, uint64_t n,
+                    uint32_t n_blocks, uint32_t n_parts, size_t ws_bytes, Plan *plan) {
+  if ((int)key < 0 || (int)key > 5) return fail(ctx, PSS_ERR_INVALID, "unknown key type");
+  if ((int)val != PSS_VAL_NONE && (int)val != PSS_VAL_U32)
+    return fail(ctx, PSS_ERR_INVALID, "unknown value type");
+  if ((n_blocks == 0) != (n_parts == 0))
+    return fail(ctx, PSS_ERR_INVALID, "n_blocks and n_parts must both be 0 (auto) or both > 0");
+  if (n > PSS_MAX_KEYS) return fail(ctx, PSS_ERR_UNSUPPORTED, "n >= 2^31 is not supported");
+  if (n_blocks > PSS_MAX_BLOCKS) return fail(ctx, PSS_ERR_UNSUPPORTED, "n_blocks > 2048");
+  if (n_parts > PSS_MAX_PARTS) return fail(ctx, PSS_ERR_UNSUPPORTED, "n_parts > 4194304");
+  const size_t kb = (size_t)pss::key_bytes((int)key);
+  if (n > 0) {
+    if (!keys_in || !keys_out) return fail(ctx, PSS_ERR_INVALID, "null key pointer");
+    if (overlaps(keys_in, n * kb, keys_out, n * kb))
+      return fail(ctx, PSS_ERR_INVALID, "keys_in and keys_out overlap (the sort is out of place)");
+    if (val == PSS_VAL_U32) {
+      if (!vals_in || !vals_out) return fail(ctx, PSS_ERR_INVALID, "null value pointer");
+      if (overlaps(vals_in, n * 4, vals_out, n * 4))
+        return fail(ctx, PSS_ERR_INVALID, "vals_in and vals_out overlap");
+      if (overlaps(keys_out, n * kb, vals_out, n * 4) || overlaps(keys_in, n * kb, vals_out, n * 4) ||
+          overlaps(vals_in, n * 4, keys_out, n * kb))
+        return fail(ctx, PSS_ERR_INVALID, "key and value arrays overlap");
+    }
+  }
+  std::string err;
+  const pss_status ps = make_plan(key, val, n, n_blocks, n_parts, plan, &err);
+  if (ps != PSS_OK) return fail(ctx, ps, err);
+  if (ws_bytes != SIZE_MAX && ws_bytes < plan->total) {
+    char m[160];
+    snprintf(m, sizeof m, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
+             plan->total);
+    return fail(ctx, PSS_ERR_WORKSPACE, m);
+  }
+  return PSS_OK;
+}
+
+#define PSS_TRY(expr, what)                       \
+  do {                                            \
+    const hipError_t e_ = (expr);                 \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+  } while (0)
+
+// Tile sort plus the merge passes of every segment.  bufs[q] receives the
+// output of pass q (bufs[0] the tile sort); values likewise.
+pss_status run_segment_sort(pss_ctx *ctx, const Plan &p, int kt, const void *keys_in,
+                            const uint32_t *vals_in, void *const *kbuf, uint32_t *const *vbuf,
+                            int final_last, uint32_t *table, hipStream_t s) {
+  const size_t P = p.passes.size();
+  PSS_TRY(pss::launch_tile_sort(kt, p.kv, keys_in, vals_in, kbuf[0], vbuf[0], p.n, p.seg_len,
+                                final_last && P == 0, s),
+          "tile sort launch");
+  for (size_t q = 1; q <= P; ++q) {
+    const pss::RunGeom &g = p.passes[q - 1];
+    PSS_TRY(pss::launch_corank(kt, kbuf[q - 1], g, table, nullptr, nullptr, s), "split search launch");
+    PSS_TRY(pss::launch_merge(kt, p.kv, kbuf[q - 1], vbuf[q - 1], kbuf[q], vbuf[q], g, table, nullptr,
+                              final_last && q == P, s),
+            "merge launch");
+  }
+  return PSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pss_status pss_create(int device, pss_ctx **out) {
+  if (!out) return fail(nullptr, PSS_ERR_INVALID, "null output handle");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
+  if (device < 0 || device >= count) return fail(nullptr, PSS_ERR_HIP, "no such HIP device");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  pss_ctx *c = new (std::nothrow) pss_ctx;
+  if (!c) return fail(nullptr, PSS_ERR_OOM, "out of host memory");
+  c->device = device;
+  *out = c;
+  return PSS_OK;
+}
+
+void pss_destroy(pss_ctx *ctx) { delete ctx; }
+
+const char *pss_status_string(pss_status s) {
+  switch (s) {
+    case PSS_OK: return "PSS_OK";
+    case PSS_ERR_INVALID: return "PSS_ERR_INVALID";
+    case PSS_ERR_UNSUPPORTED: return "PSS_ERR_UNSUPPORTED";
+    case PSS_ERR_OOM: return "PSS_ERR_OOM";
+    case PSS_ERR_HIP: return "PSS_ERR_HIP";
+    case PSS_ERR_WORKSPACE: return "PSS_ERR_WORKSPACE";
+    default: return "PSS_ERR_UNKNOWN";
+  }
+}
+
+const char *pss_last_error(const pss_ctx *ctx) {
+  return ctx ? ctx->last_error.c_str() : g_thread_error.c_str();
+}
+
+pss_status pss_validate(pss_key_t key, pss_val_t val, const void *keys_in, const void *keys_out,
+                        const void *vals_in, const void *vals_out, uint64_t n, uint32_t n_blocks,
+                        uint32_t n_parts, size_t ws_bytes) {
+  Plan p;
+  return validate(nullptr, key, val, keys_in, keys_out, vals_in, vals_out, n, n_blocks, n_parts,
+                  ws_bytes, &p);
+}
+
+pss_status pss_workspace_bytes(const pss_ctx *ctx, pss_key_t key, pss_val_t val, uint64_t n,
+                               uint32_t n_blocks, uint32_t n_parts, size_t *bytes) {
+  if (!bytes) return fail(ctx, PSS_ERR_INVALID, "null output pointer");
+  Plan p;
+  // enum, mode and limit checks only (no arrays exist yet)
+  const pss_status s = validate(ctx, key, val, nullptr, nullptr, nullptr, nullptr, 0, n_blocks,
+                                n_parts, SIZE_MAX, &p);
+  if (s != PSS_OK) return s;
+  if (n > PSS_MAX_KEYS) return fail(ctx, PSS_ERR_UNSUPPORTED, "n >= 2^31 is not supported");
+  std::string err;
+  const pss_status ps = make_plan(key, val, n, n_blocks, n_parts, &p, &err);
+  if (ps != PSS_OK) return fail(ctx, ps, err);
+  *bytes = p.total;
+  return PSS_OK;
+}
+
+pss_status pss_plan_describe(pss_key_t key, pss_val_t val, uint64_t n, uint32_t n_blocks,
+                             uint32_t n_parts, char *buf, size_t buf_len) {
+  if (!buf || buf_len == 0) return fail(nullptr, PSS_ERR_INVALID, "null buffer");
+  size_t ws = 0;
+  const pss_status s = pss_workspace_bytes(nullptr, key, val, n, n_blocks, n_parts, &ws);
+  if (s != PSS_OK) return s;
+  Plan p;
+  std::string err;
+  make_plan(key, val, n, n_blocks, n_parts, &p, &err);
+  std::string j = "{\"mode\": \"";
+  j += p.paper ? "paper" : "auto";
+  j += "\", \"tile\": " + std::to_string(pss::kTile) + ", \"part\": " + std::to_string(pss::kPart);
+  std::string fans;
+  for (size_t i = 0; i < p.passes.size(); ++i)
+    fans += (i ? ", " : "") + std::to_string(p.passes[i].fan);
+  if (p.paper) {
+    j += ", \"passes\": [" + std::to_string(n_blocks) + "], \"block_passes\": [" + fans + "]";
+  } else {
+    j += ", \"passes\": [" + fans + "], \"block_passes\": []";
+  }
+  const size_t sweeps = (n ? 1 : 0) + p.passes.size() + (p.paper && n ? 1 : 0);
+  j += ", \"n_blocks\": " + std::to_string(n_blocks) + ", \"n_parts\": " + std::to_string(n_parts);
+  j += ", \"hbm_passes\": " + std::to_string(sweeps) + ", \"workspace_bytes\": " + std::to_string(ws) + "}";
+  if (j.size() + 1 > buf_len) return fail(nullptr, PSS_ERR_INVALID, "buffer too small");
+  memcpy(buf, j.c_str(), j.size() + 1);
+  return PSS_OK;
+}
+
+pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys_in,
+                    void *keys_out, const uint32_t *vals_in, uint32_t *vals_out, uint64_t n,
+                    uint32_t n_blocks, uint32_t n_parts, void *ws, size_t ws_bytes,
+                    void *stream) {
+  Plan p;
+  pss_status st = validate(ctx, key, val, keys_in, keys_out, vals_in, vals_out, n, n_blocks,
+                           n_parts, ws_bytes, &p);
+  if (st != PSS_OK) return st;
+  if (!ctx) return fail(nullptr, PSS_ERR_INVALID, "null context");
+  if (n == 0) return PSS_OK;
+  if (!ws) return fail(ctx, PSS_ERR_WORKSPACE, "null workspace");
+  PSS_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  char *w = (char *)ws;
+  uint32_t *table = (uint32_t *)(w + p.off_table);
+  const int kt = (int)key;
+  const size_t P = p.passes.size();
+
+  if (!p.paper) {
+    // bufs[P] = output, bufs[P-1] = workspace, alternating backwards
+    std::vector<void *> kb(P + 1);
+    std::vector<uint32_t *> vb(P + 1, nullptr);
+    for (size_t q = 0; q <= P; ++q) {
+      const bool to_out = ((P - q) % 2) == 0;
+      kb[q] = to_out ? keys_out : (void *)(w + p.off_keys0);
+      if (p.kv) vb[q] = to_out ? vals_out : (uint32_t *)(w + p.off_vals0);
+    }
+    st = run_segment_sort(ctx, p, kt, keys_in, vals_in, kb.data(), vb.data(), 1, table, s);
+    if (st != PSS_OK) return st;
+  } else {
+    // block sort ends in workspace buffer 0; the cross-block merge writes out
+    std::vector<void *> kb(P + 1);
+    std::vector<uint32_t *> vb(P + 1, nullptr);
+    for (size_t q = 0; q <= P; ++q) {
+      const bool even = ((P - q) % 2) == 0;
+      kb[q] = even ? (void *)(w + p.off_keys0) : (void *)(w + p.off_keys1);
+      if (p.kv) vb[q] = even ? (uint32_t *)(w + p.off_vals0) : (uint32_t *)(w + p.off_vals1);
+    }
+    st = run_segment_sort(ctx, p, kt, keys_in, vals_in, kb.data(), vb.data(), 0, table, s);
+    if (st != PSS_OK) return st;
+    uint64_t *sizes = (uint64_t *)(w + p.off_sizes);
+    uint64_t *offsets = (uint64_t *)(w + p.off_offsets);
+    PSS_TRY(pss::launch_corank(kt, kb[P], p.top, table, nullptr, nullptr, s), "splitter launch");
+    PSS_TRY(pss::launch_partition_offsets(p.top, table, sizes, offsets, s), "offset scan launch");
+    PSS_TRY(pss::launch_merge(kt, p.kv, kb[P], vb[P], keys_out, vals_out, p.top, table, offsets, 1, s),
+            "merge launch");
+  }
+  return PSS_OK;
+}
+
+pss_status pss_device_check(pss_ctx *ctx, uint32_t *code) {
+  if (!ctx || !code) return fail(ctx, PSS_ERR_INVALID, "null argument");
+  PSS_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  PSS_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  PSS_TRY(pss::read_device_error(code, true), "reading the device error word");
+  return PSS_OK;
+}
+
+pss_status pss_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, uint64_t n,
+                         uint32_t n_blocks, uint32_t n_parts, void *sorted_blocks, void *pivots,
+                         uint64_t *counts, uint64_t *split, uint64_t *offsets, void *ws,
+                         size_t ws_bytes, void *stream) {
+  if (n_blocks == 0 || n_parts == 0)
+    return fail(ctx, PSS_ERR_INVALID, "pss_splitters needs n_blocks > 0 and n_parts > 0");
+  Plan p;
+  // keys_out is not used here; validate the key input against a disjoint dummy
+  const char dummy = 0;
+  pss_status st = validate(ctx, key, PSS_VAL_NONE, keys_in, n ? &dummy : nullptr, nullptr, nullptr,
+                           n, n_blocks, n_parts, ws_bytes, &p);
+  if (st != PSS_OK) return st;
+  if (!ctx) return fail(nullptr, PSS_ERR_INVALID, "null context");
+  if (n > 0 && !ws) return fail(ctx, PSS_ERR_WORKSPACE, "null workspace");
+  if (n_parts > 1 && (pivots != nullptr) != (counts != nullptr))
+    return fail(ctx, PSS_ERR_INVALID, "pivots and counts must be given together");
+  PSS_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int kt = (int)key;
+  const int kbytes = pss::key_bytes(kt);
+  if (n == 0) {
+    if (counts && n_parts > 1)
+      PSS_TRY(hipMemsetAsync(counts, 0, (n_parts - 1) * sizeof(uint64_t), s), "memset");
+    if (pivots && n_parts > 1)
+      PSS_TRY(hipMemsetAsync(pivots, 0, (size_t)(n_parts - 1) * kbytes, s), "memset");
+    if (split) PSS_TRY(hipMemsetAsync(split, 0, (size_t)n_blocks * (n_parts + 1) * 8, s), "memset");
+    if (offsets) PSS_TRY(hipMemsetAsync(offsets, 0, ((size_t)n_parts + 1) * 8, s), "memset");
+    return PSS_OK;
+  }
+  char *w = (char *)ws;
+  uint32_t *table = (uint32_t *)(w + p.off_table);
+  const size_t P = p.passes.size();
+  std::vector<void *> kb(P + 1);
+  std::vector<uint32_t *> vb(P + 1, nullptr);
+  for (size_t q = 0; q <= P; ++q) {
+    const bool even = ((P - q) % 2) == 0;
+    kb[q] = even ? (void *)(w + p.off_keys0) : (void *)(w + p.off_keys1);
+  }
+  st = run_segment_sort(ctx, p, kt, keys_in, nullptr, kb.data(), vb.data(), 0, table, s);
+  if (st != PSS_OK) return st;
+  uint64_t *sizes = (uint64_t *)(w + p.off_sizes);
+  uint64_t *offs = (uint64_t *)(w + p.off_offsets);
+  // pivots and counts are written by the splitter search (both or neither)
+  void *piv_dev = n_parts > 1 ? pivots : nullptr;
+  uint64_t *cnt_dev = n_parts > 1 ? counts : nullptr;
+  PSS_TRY(pss::launch_corank(kt, kb[P], p.top, table, piv_dev, cnt_dev, s), "splitter launch");
+  PSS_TRY(pss::launch_partition_offsets(p.top, table, sizes, offs, s), "offset scan launch");
+  if (offsets)
+    PSS_TRY(hipMemcpyAsync(offsets, offs, ((size_t)n_parts + 1) * 8, hipMemcpyDeviceToDevice, s),
+            "offset copy");
+  if (split) PSS_TRY(pss::launch_split_table(p.top, table, split, s), "split table launch");
+  if (sorted_blocks) PSS_TRY(pss::launch_unmap_copy(kt, kb[P], sorted_blocks, n, s), "block copy");
+  return PSS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal declarations shared by the C-ABI layer (pss_api.hip) and the HIP
+// kernels (pss_kernels.hip).  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace pss {
+
+// Step 1 tile sort: one workgroup sorts kTile keys held in LDS.
+constexpr int kTileThreads = 512;
+constexpr int kTileItems = 16;
+constexpr int kTile = kTileThreads * kTileItems;  // 8192 keys
+
+// Step 4 merge: one workgroup merges one partition of at most kPart keys.
+constexpr int kMergeThreads = 512;
+constexpr int kMergeItems = 16;
+constexpr int kPart = kMergeThreads * kMergeItems;  // 8192 keys
+
+// Step 2 splitter search: one 64-lane workgroup per splitter.
+constexpr int kCorankThreads = 64;
+// Largest number of runs one splitter search handles (LDS-bound: the
+// candidate set of one level is below 3 * runs).
+constexpr uint32_t kMaxRuns = 2048;
+// Runs merged by one pass of the automatic plan (powers of two).
+constexpr int kMaxFanLog2 = 5;
+
+// Geometry of one merge pass.  The array is cut into uniform segments of
+// seg_len keys (the last one short); inside a segment, sorted runs of run_len
+// keys are merged in groups of `fan` runs, each group's output cut into
+// partitions of part_len keys.  In paper mode there is exactly one group (the
+// whole array, runs = the paper's blocks) and partition boundaries are the
+// paper's r_k = floor(k N / n_P), each paper partition further cut into
+// sub_per_part chunks of at most part_len keys.
+struct RunGeom {
+  uint64_t n;
+  uint64_t seg_len;
+  uint64_t run_len;
+  uint32_t fan;
+  uint64_t group_len;       // min(fan * run_len, seg_len)
+  uint64_t groups_per_seg;  // ceil(seg_len / group_len)
+  uint64_t n_groups;        // n_segments * groups_per_seg
+  uint32_t rows_per_group;  // partitions per full group + 1
+  uint32_t part_len;
+  int paper;
+  uint32_t n_parts;       // paper mode: n_P
+  uint32_t sub_per_part;  // paper mode: chunks per paper partition
+  uint64_t total_rows() const {
+    return paper ? (uint64_t)n_parts * sub_per_part + 1 : n_groups * rows_per_group;
+  }
+  uint64_t total_parts() const {
+    return paper ? (uint64_t)n_parts * sub_per_part : n_groups * (rows_per_group - 1);
+  }
+};
+
+// Bits of the device error word (see read_device_error).
+constexpr uint32_t kErrCandidates = 1u;  // splitter search: candidate set overflow
+constexpr uint32_t kErrBracket = 2u;     // splitter search: target outside bracket
+constexpr uint32_t kErrSplitRow = 4u;    // merge: split row not inside its run
+constexpr uint32_t kErrPartSize = 8u;    // merge: segments do not add up to the partition
+
+// Synchronous read (and optional clear) of the device error word.
+hipError_t read_device_error(uint32_t *code, bool clear);
+
+// key-type codes (same numbering as pss_key_t)
+inline int key_bytes(int kt) { return (kt == 0 || kt == 1 || kt == 4) ? 4 : 8; }
+
+hipError_t launch_tile_sort(int kt, bool kv, const void *in, const uint32_t *vin, void *out,
+                            uint32_t *vout, uint64_t n, uint64_t seg_len, int final_pass,
+                            hipStream_t s);
+hipError_t launch_corank(int kt, const void *src, const RunGeom &g, uint32_t *table,
+                         void *pivots, uint64_t *counts, hipStream_t s);
+hipError_t launch_merge(int kt, bool kv, const void *src, const uint32_t *vsrc, void *dst,
+                        uint32_t *vdst, const RunGeom &g, const uint32_t *table,
+                        const uint64_t *part_offsets, int final_pass, hipStream_t s);
+hipError_t launch_partition_offsets(const RunGeom &g, const uint32_t *table, uint64_t *sizes,
+                                    uint64_t *offsets, hipStream_t s);
+hipError_t launch_split_table(const RunGeom &g, const uint32_t *table, uint64_t *split,
+                              hipStream_t s);
+hipError_t launch_unmap_copy(int kt, const void *src, void *dst, uint64_t n, hipStream_t s);
+
+}  // namespace pss

@@ -1,0 +1,974 @@
+// HIP kernels for gfx950 (MI355X) implementing the hot path of parallel
+// samplesort with exact splitting (PSES), arXiv 2305.05245, Section 2:
+//
+//   K0  order-preserving key map fused into the first load and the last store
+//   K1  step 1 ("sorting each block"): LDS-resident tile sort
+//   K2  step 2 (PSES pivot selection, Section 2.3, Eq. 1 and Eq. 2): exact
+//       splitting by a bracketed bit-by-bit co-rank search over all sorted runs
+//   K3  step 3 (partitioning): the split positions of every run, one table row
+//       per splitter; a sorted run's partitions are contiguous, so no data moves
+//   K4  offsets of the merged partitions: a device reduction and exclusive scan
+//   K5  step 4 (multiway merging of partitions): one workgroup per partition
+//       gathers the partition's segments from all runs into LDS and merges them
+//       with rounds of stable merge-path merges, then stores coalesced.
+//
+// Keys are compared only as unsigned integers after the K0 map (signed ints:
+// sign bit flipped; floats: IEEE totalOrder map), so every comparison is an
+// integer comparison and the output is bit-exact.
+#include "pss_internal.hpp"
+
+#include <type_traits>
+
+namespace pss {
+
+// Set (bitwise or) by a kernel that finds one of its invariants broken; the
+// kernel then stops before touching memory outside its own partition.
+__device__ uint32_t g_device_error = 0;
+
+namespace {
+
+__device__ __forceinline__ void report(uint32_t code) { atomicOr(&g_device_error, code); }
+
+// ------------------------------------------------------------------ K0 ----
+template <int KT> struct Key;
+template <> struct Key<0> {  // uint32
+  using U = uint32_t;
+  static __device__ __forceinline__ U map(U x) { return x; }
+  static __device__ __forceinline__ U unmap(U x) { return x; }
+};
+template <> struct Key<1> {  // int32: flip the sign bit
+  using U = uint32_t;
+  static __device__ __forceinline__ U map(U x) { return x ^ 0x80000000u; }
+  static __device__ __forceinline__ U unmap(U x) { return x ^ 0x80000000u; }
+};
+template <> struct Key<2> {  // uint64
+  using U = uint64_t;
+  static __device__ __forceinline__ U map(U x) { return x; }
+  static __device__ __forceinline__ U unmap(U x) { return x; }
+};
+template <> struct Key<3> {  // int64
+  using U = uint64_t;
+  static __device__ __forceinline__ U map(U x) { return x ^ 0x8000000000000000ull; }
+  static __device__ __forceinline__ U unmap(U x) { return x ^ 0x8000000000000000ull; }
+};
+template <> struct Key<4> {  // float32, IEEE totalOrder: negative -> all bits
+  using U = uint32_t;        // inverted, otherwise the sign bit set
+  static __device__ __forceinline__ U map(U x) {
+    return (x & 0x80000000u) ? ~x : (x | 0x80000000u);
+  }
+  static __device__ __forceinline__ U unmap(U x) {
+    return (x & 0x80000000u) ? (x & 0x7fffffffu) : ~x;
+  }
+};
+template <> struct Key<5> {  // float64, IEEE totalOrder
+  using U = uint64_t;
+  static __device__ __forceinline__ U map(U x) {
+    return (x & 0x8000000000000000ull) ? ~x : (x | 0x8000000000000000ull);
+  }
+  static __device__ __forceinline__ U unmap(U x) {
+    return (x & 0x8000000000000000ull) ? (x & 0x7fffffffffffffffull) : ~x;
+  }
+};
+
+template <typename U>
+__device__ __forceinline__ U unmap_runtime(U x, int kt) {
+  if constexpr (sizeof(U) == 4) {
+    switch (kt) {
+      case 1: return Key<1>::unmap(x);
+      case 4: return Key<4>::unmap(x);
+      default: return x;
+    }
+  } else {
+    switch (kt) {
+      case 3: return Key<3>::unmap(x);
+      case 5: return Key<5>::unmap(x);
+      default: return x;
+    }
+  }
+}
+
+template <typename U> __device__ __forceinline__ constexpr U key_max() { return ~U(0); }
+
+// LDS index with one pad slot after every 16 keys, so that a thread reading or
+// writing its 16 consecutive keys does not hit the same bank as its neighbours.
+__device__ __forceinline__ uint32_t pad16(uint32_t i) { return i + (i >> 4); }
+
+// ----------------------------------------------------- sorting networks ----
+// Index pairs of Batcher's odd-even merge sort on N registers (unstable,
+// keys only) and of odd-even transposition sort (stable: only neighbours are
+// compared and equal keys are never swapped), generated at compile time.
+template <int N> constexpr int batcher_pairs() {
+  int c = 0;
+  for (int p = 1; p < N; p <<= 1)
+    for (int k = p; k >= 1; k >>= 1)
+      for (int j = k % p; j + k < N; j += 2 * k)
+        for (int i = 0; i < k && i + j + k < N; ++i)
+          if ((i + j) / (2 * p) == (i + j + k) / (2 * p)) ++c;
+  return c;
+}
+template <int N> struct BatcherNet {
+  int a[batcher_pairs<N>()];
+  int b[batcher_pairs<N>()];
+  constexpr BatcherNet() : a(), b() {
+    int c = 0;
+    for (int p = 1; p < N; p <<= 1)
+      for (int k = p; k >= 1; k >>= 1)
+        for (int j = k % p; j + k < N; j += 2 * k)
+          for (int i = 0; i < k && i + j + k < N; ++i)
+            if ((i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+              a[c] = i + j;
+              b[c] = i + j + k;
+              ++c;
+            }
+  }
+};
+template <int N> constexpr int transposition_pairs() { return (N / 2) * ((N + 1) / 2) + ((N - 1) / 2) * (N / 2); }
+template <int N> struct TranspositionNet {
+  int a[transposition_pairs<N>()];
+  constexpr TranspositionNet() : a() {
+    int c = 0;
+    for (int phase = 0; phase < N; ++phase)
+      for (int i = phase & 1; i + 1 < N; i += 2) a[c++] = i;
+  }
+};
+
+template <typename U, bool KV, int N>
+__device__ __forceinline__ void register_sort(U (&k)[N], uint32_t (&v)[KV ? N : 1]) {
+  if constexpr (!KV) {
+    constexpr BatcherNet<N> net{};
+#pragma unroll
+    for (int c = 0; c < batcher_pairs<N>(); ++c) {
+      const U x = k[net.a[c]], y = k[net.b[c]];
+      k[net.a[c]] = x < y ? x : y;
+      k[net.b[c]] = x < y ? y : x;
+    }
+  } else {
+    constexpr TranspositionNet<N> net{};
+#pragma unroll
+    for (int c = 0; c < transposition_pairs<N>(); ++c) {
+      const int i = net.a[c];
+      const bool s = k[i + 1] < k[i];
+      const U x = k[i], y = k[i + 1];
+      const uint32_t vx = v[i], vy = v[i + 1];
+      k[i] = s ? y : x;
+      k[i + 1] = s ? x : y;
+      v[i] = s ? vy : vx;
+      v[i + 1] = s ? vx : vy;
+    }
+  }
+}
+
+// --------------------------------------------------------------- K1 -------
+// One workgroup sorts one tile of at most kTile keys of one segment.  Keys are
+// mapped on load (K0), each thread sorts 16 consecutive keys in registers, then
+// log2(kTile/16) rounds of stable merge-path merges run through LDS.  A short
+// tile is padded with the largest key; pads sit after every real key (for
+// key-value sorts the network and merges are stable, so pads stay last).
+template <int KT, bool KV>
+__global__ __launch_bounds__(kTileThreads) void tile_sort_kernel(
+    const typename Key<KT>::U *__restrict__ in, const uint32_t *__restrict__ vin,
+    typename Key<KT>::U *__restrict__ out, uint32_t *__restrict__ vout, uint64_t n,
+    uint64_t seg_len, uint64_t tiles_per_seg, int final_pass) {
+  using U = typename Key<KT>::U;
+  constexpr uint32_t P = kTile + kTile / 16;
+  __shared__ U sk[P];
+  __shared__ uint32_t sv[KV ? P : 1];
+
+  const uint32_t tid = threadIdx.x;
+  const uint64_t t = blockIdx.x;
+  const uint64_t seg = t / tiles_per_seg, j = t % tiles_per_seg;
+  const uint64_t seg_start = seg * seg_len;
+  if (seg_start >= n) return;
+  const uint64_t seg_end = seg_start + seg_len < n ? seg_start + seg_len : n;
+  const uint64_t start = seg_start + j * (uint64_t)kTile;
+  if (start >= seg_end) return;
+  const uint32_t len = (uint32_t)(seg_end - start < (uint64_t)kTile ? seg_end - start : kTile);
+
+#pragma unroll
+  for (int i = 0; i < kTileItems; ++i) {
+    const uint32_t idx = i * kTileThreads + tid;
+    U k = key_max<U>();
+    uint32_t v = 0;
+    if (idx < len) {
+      k = Key<KT>::map(in[start + idx]);
+      if constexpr (KV) v = vin[start + idx];
+    }
+    sk[pad16(idx)] = k;
+    if constexpr (KV) sv[pad16(idx)] = v;
+  }
+  __syncthreads();
+
+  U rk[kTileItems];
+  uint32_t rv[KV ? kTileItems : 1];
+#pragma unroll
+  for (int i = 0; i < kTileItems; ++i) {
+    const uint32_t idx = tid * kTileItems + i;
+    rk[i] = sk[pad16(idx)];
+    if constexpr (KV) rv[i] = sv[pad16(idx)];
+  }
+  register_sort<U, KV, kTileItems>(rk, rv);
+
+  for (uint32_t L = kTileItems; L < (uint32_t)kTile; L *= 2) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kTileItems; ++i) {
+      const uint32_t idx = tid * kTileItems + i;
+      sk[pad16(idx)] = rk[i];
+      if constexpr (KV) sv[pad16(idx)] = rv[i];
+    }
+    __syncthreads();
+    // merge path: how many of this thread's first output position's
+    // predecessors come from the left run A (ties go to A: stable)
+    const uint32_t pos = tid * kTileItems;
+    const uint32_t diag = pos & (2 * L - 1);
+    const uint32_t a0 = pos - diag, b0 = a0 + L;
+    uint32_t lo = diag > L ? diag - L : 0, hi = diag < L ? diag : L;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (sk[pad16(a0 + mid)] <= sk[pad16(b0 + diag - 1 - mid)]) lo = mid + 1;
+      else hi = mid;
+    }
+    uint32_t ai = lo, bi = diag - lo;
+    U ka = sk[pad16(a0 + (ai < L ? ai : L - 1))];
+    U kb = sk[pad16(b0 + (bi < L ? bi : L - 1))];
+    uint32_t va = 0, vb = 0;
+    if constexpr (KV) {
+      va = sv[pad16(a0 + (ai < L ? ai : L - 1))];
+      vb = sv[pad16(b0 + (bi < L ? bi : L - 1))];
+    }
+#pragma unroll
+    for (int i = 0; i < kTileItems; ++i) {
+      const bool takeA = ai < L && (bi >= L || ka <= kb);
+      rk[i] = takeA ? ka : kb;
+      if constexpr (KV) rv[i] = takeA ? va : vb;
+      uint32_t nxt = takeA ? a0 + ai + 1 : b0 + bi + 1;
+      nxt = nxt < (uint32_t)kTile ? nxt : (uint32_t)kTile - 1;
+      const U nk = sk[pad16(nxt)];
+      ka = takeA ? nk : ka;
+      kb = takeA ? kb : nk;
+      if constexpr (KV) {
+        const uint32_t nv = sv[pad16(nxt)];
+        va = takeA ? nv : va;
+        vb = takeA ? vb : nv;
+      }
+      ai += takeA ? 1u : 0u;
+      bi += takeA ? 0u : 1u;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kTileItems; ++i) {
+    const uint32_t idx = tid * kTileItems + i;
+    sk[pad16(idx)] = rk[i];
+    if constexpr (KV) sv[pad16(idx)] = rv[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kTileItems; ++i) {
+    const uint32_t idx = i * kTileThreads + tid;
+    if (idx < len) {
+      const U k = sk[pad16(idx)];
+      out[start + idx] = final_pass ? Key<KT>::unmap(k) : k;
+      if constexpr (KV) vout[start + idx] = sv[pad16(idx)];
+    }
+  }
+}
+
+// ----------------------------------------------------- run geometry ------
+struct GroupInfo {
+  uint64_t start;  // first key of the group
+  uint64_t len;    // keys in the group (0 = no such group)
+  uint64_t gi;     // group index (table block index)
+};
+
+__device__ __forceinline__ GroupInfo group_of(const RunGeom &g, uint64_t gi) {
+  GroupInfo r;
+  r.gi = gi;
+  const uint64_t seg = gi / g.groups_per_seg, gg = gi % g.groups_per_seg;
+  const uint64_t seg_start = seg * g.seg_len;
+  const uint64_t seg_len = seg_start < g.n ? (g.n - seg_start < g.seg_len ? g.n - seg_start : g.seg_len) : 0;
+  const uint64_t goff = gg * g.group_len;
+  r.start = seg_start + goff;
+  r.len = goff < seg_len ? (seg_len - goff < g.group_len ? seg_len - goff : g.group_len) : 0;
+  return r;
+}
+
+// r_k = floor(k N / n_P) (the paper's k N / n_P in exact integer arithmetic)
+__device__ __forceinline__ uint64_t paper_rank(const RunGeom &g, uint64_t k) {
+  return (uint64_t)(((unsigned __int128)k * g.n) / g.n_parts);
+}
+
+// Group and target rank of table row `row`: uniform partitions of part_len
+// keys, or (paper mode) chunks of at most part_len keys inside each of the
+// paper's partitions.
+struct RowInfo {
+  GroupInfo grp;
+  uint64_t rank;
+  uint32_t *out;
+};
+
+__device__ __forceinline__ RowInfo row_info(const RunGeom &g, uint64_t row, uint32_t *table) {
+  RowInfo ri;
+  if (!g.paper) {
+    const uint64_t gi = row / g.rows_per_group, k = row % g.rows_per_group;
+    ri.grp = group_of(g, gi);
+    const uint64_t r = k * g.part_len;
+    ri.rank = r < ri.grp.len ? r : ri.grp.len;
+  } else {
+    ri.grp.gi = 0;
+    ri.grp.start = 0;
+    ri.grp.len = g.n;
+    const uint64_t last = (uint64_t)g.n_parts * g.sub_per_part;
+    if (row >= last) {
+      ri.rank = g.n;
+    } else {
+      const uint64_t p = row / g.sub_per_part, i = row % g.sub_per_part;
+      const uint64_t rp = paper_rank(g, p), rp1 = paper_rank(g, p + 1);
+      const uint64_t r = rp + i * g.part_len;
+      ri.rank = r < rp1 ? r : rp1;
+    }
+  }
+  ri.out = table + row * g.fan;
+  return ri;
+}
+
+__device__ __forceinline__ uint32_t run_length(uint64_t group_len, uint64_t run_len, uint32_t b) {
+  const uint64_t off = (uint64_t)b * run_len;
+  if (off >= group_len) return 0;
+  const uint64_t rem = group_len - off;
+  return (uint32_t)(rem < run_len ? rem : run_len);
+}
+
+// ------------------------------------------------------- wave helpers ----
+// Exclusive scan of a[0..n) in place, total into a[n]; one 64-lane workgroup.
+__device__ void wave_exclusive_scan(uint32_t *a, uint32_t n) {
+  const uint32_t lane = threadIdx.x;
+  const uint32_t per = (n + 63) / 64;
+  const uint32_t beg = lane * per < n ? lane * per : n;
+  const uint32_t end = beg + per < n ? beg + per : n;
+  uint32_t s = 0;
+  for (uint32_t i = beg; i < end; ++i) s += a[i];
+  uint32_t x = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if ((int)lane >= d) x += y;
+  }
+  const uint32_t total = __shfl(x, 63, 64);
+  uint32_t e = x - s;
+  for (uint32_t i = beg; i < end; ++i) {
+    const uint32_t v = a[i];
+    a[i] = e;
+    e += v;
+  }
+  if (lane == 0) a[n] = total;
+}
+
+// Exclusive scan of a[0..n) in place, total into a[n]; whole workgroup.
+// `wsum` needs blockDim.x/64 + 1 entries.
+__device__ void block_exclusive_scan(uint32_t *a, uint32_t n, uint32_t *wsum) {
+  const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+  const uint32_t lane = tid & 63, wid = tid >> 6, nw = nthr >> 6;
+  const uint32_t per = (n + nthr - 1) / nthr;
+  const uint32_t beg = tid * per < n ? tid * per : n;
+  const uint32_t end = beg + per < n ? beg + per : n;
+  uint32_t s = 0;
+  for (uint32_t i = beg; i < end; ++i) s += a[i];
+  uint32_t x = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if ((int)lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wid] = x;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t run = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+      const uint32_t v = wsum[w];
+      wsum[w] = run;
+      run += v;
+    }
+    wsum[nw] = run;
+  }
+  __syncthreads();
+  uint32_t e = x - s + wsum[wid];
+  for (uint32_t i = beg; i < end; ++i) {
+    const uint32_t v = a[i];
+    a[i] = e;
+    e += v;
+  }
+  if (tid == 0) a[n] = wsum[nw];
+  __syncthreads();
+}
+
+// --------------------------------------------------------------- K2/K3 ---
+// Exact co-rank of one target rank r over the F sorted runs of one group:
+// t_b = number of keys of run b among the r smallest keys of the group, where
+// equal keys are ordered by run index, then position (lowest run first).
+// This realises the paper's exact splitting: sum_b t_b = r exactly, all keys
+// below the pivot go left, and of the keys equal to it exactly c_k go left,
+// taken from the lowest-numbered run first.
+//
+// Search (our GPU design, not the paper's): positions are fixed one bit at a
+// time from the most significant.  At level j the samples are the keys at
+// positions i*2^j - 1.  The prefix of the Q smallest level-j samples, V_j(Q),
+// is known to lie between V_j(Q_lo) and V_j(Q_hi) with
+//   Q_lo(j) = max(0, floor((r - (2^j - 1)(F - 1)) / 2^j)),
+//   Q_hi(j) = min(floor(r / 2^j), number of level-j samples),
+// and V_j(Q)_b is within [2 V_{j+1}(Q_lo(j+1))_b, 2 V_{j+1}(Q_hi(j+1))_b + 1].
+// So each level loads fewer than 3F candidate samples, sorts them in LDS and
+// reads both prefixes off; at level 0, Q_lo = Q_hi = r and V_0(r) = t.
+template <typename U, uint32_t MAXF>
+__global__ __launch_bounds__(kCorankThreads) void corank_kernel(
+    const U *__restrict__ src, RunGeom g, uint32_t *__restrict__ table,
+    U *__restrict__ pivots, uint64_t *__restrict__ counts, int kt) {
+  constexpr uint32_t CMAX = MAXF <= 64 ? 256 : (MAXF <= 512 ? 2048 : 8192);
+  __shared__ U sKey[CMAX];
+  __shared__ uint32_t sTie[CMAX];
+  __shared__ uint32_t sA[MAXF], sB[MAXF], sCnt[2 * MAXF], sOff[MAXF + 1];
+
+  const uint32_t lane = threadIdx.x;
+  const uint64_t row = blockIdx.x;
+  const RowInfo ri = row_info(g, row, table);
+  const uint64_t glen = ri.grp.len, R = g.run_len, r = ri.rank;
+  const uint32_t nruns = glen ? (uint32_t)((glen + R - 1) / R) : 0;
+  const uint32_t F = g.fan;
+
+  // trivial rows: nothing or everything taken
+  const bool trivial = r == 0 || r >= glen;
+  if (trivial) {
+    for (uint32_t b = lane; b < nruns; b += 64) sA[b] = r == 0 ? 0u : run_length(glen, R, b);
+    __syncthreads();
+  }
+  const uint32_t maxlen = trivial ? 1u : (uint32_t)(R < glen ? R : glen);
+  const uint32_t lastlen = trivial ? 0u : run_length(glen, R, nruns - 1);
+  const int J = trivial ? 0 : 32 - __clz(maxlen);
+  if (!trivial) {
+    for (uint32_t b = lane; b < nruns; b += 64) {
+      sA[b] = 0;
+      sB[b] = 0;
+    }
+    __syncthreads();
+  }
+
+  auto q_lo_at = [&](int j) -> uint64_t {
+    const int64_t num = (int64_t)r - (int64_t)((((uint64_t)1 << j) - 1) * (uint64_t)(nruns - 1));
+    return num > 0 ? ((uint64_t)num >> j) : 0;
+  };
+
+  for (int j = J - 1; j >= 0; --j) {
+    const uint64_t h = (uint64_t)1 << j;
+    const uint64_t ns_total = (uint64_t)(nruns - 1) * (R >> j) + (lastlen >> j);
+    const uint64_t q_lo = q_lo_at(j);
+    const uint64_t q_hi = (r >> j) < ns_total ? (r >> j) : ns_total;
+    const uint64_t base = 2 * q_lo_at(j + 1);
+
+    for (uint32_t b = lane; b < nruns; b += 64) {
+      const uint32_t ns = run_length(glen, R, b) >> j;
+      const uint32_t lo_i = 2 * sA[b] + 1;
+      const uint32_t hi_i = 2 * sB[b] + 1 < ns ? 2 * sB[b] + 1 : ns;
+      sOff[b] = hi_i >= lo_i ? hi_i - lo_i + 1 : 0;
+    }
+    __syncthreads();
+    wave_exclusive_scan(sOff, nruns);
+    __syncthreads();
+    uint32_t C = sOff[nruns];
+    if (C > CMAX) {  // cannot happen while the bracket holds (C < 3 * runs)
+      if (lane == 0) report(kErrCandidates);
+      C = CMAX;
+    }
+    uint32_t Cp = 1;
+    while (Cp < C) Cp <<= 1;
+
+    for (uint32_t b = lane; b < nruns; b += 64) {
+      const uint32_t c = sOff[b + 1] - sOff[b];
+      const uint64_t run_start = ri.grp.start + (uint64_t)b * R;
+      const uint32_t first = 2 * sA[b] + 1;
+      for (uint32_t x = 0; x < c; ++x) {
+        const uint32_t s = sOff[b] + x;
+        if (s < CMAX) {
+          sKey[s] = src[run_start + (uint64_t)(first + x) * h - 1];
+          sTie[s] = (b << 20) | x;
+        }
+      }
+    }
+    for (uint32_t s = C + lane; s < Cp && s < CMAX; s += 64) {
+      sKey[s] = key_max<U>();
+      sTie[s] = 0xffffffffu;
+    }
+    for (uint32_t b = lane; b < 2 * nruns; b += 64) sCnt[b] = 0;
+    __syncthreads();
+
+    // bitonic sort of (key, tie) pairs, ascending
+    for (uint32_t k = 2; k <= Cp; k <<= 1) {
+      for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+        for (uint32_t t = lane; t < Cp / 2; t += 64) {
+          const uint32_t i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
+          const uint32_t l = i + jj;
+          const U ki = sKey[i], kl = sKey[l];
+          const uint32_t ti = sTie[i], tl = sTie[l];
+          const bool gt = ki > kl || (ki == kl && ti > tl);
+          const bool up = (i & k) == 0;
+          if (gt == up) {
+            sKey[i] = kl;
+            sKey[l] = ki;
+            sTie[i] = tl;
+            sTie[l] = ti;
+          }
+        }
+        __syncthreads();
+      }
+    }
+
+    uint64_t rho_lo = q_lo - base, rho_hi = q_hi - base;
+    if (q_lo < base || q_hi < base || rho_hi > C || rho_lo > rho_hi) {  // bracket broken
+      if (lane == 0) report(kErrBracket);
+      rho_lo = rho_lo > C ? C : rho_lo;
+      rho_hi = rho_hi > C ? C : rho_hi;
+      rho_lo = rho_lo > rho_hi ? rho_hi : rho_lo;
+    }
+    for (uint64_t s = lane; s < rho_hi; s += 64) {
+      const uint32_t b = sTie[s] >> 20;
+      atomicAdd(&sCnt[2 * b + 1], 1u);
+      if (s < rho_lo) atomicAdd(&sCnt[2 * b], 1u);
+    }
+    __syncthreads();
+    for (uint32_t b = lane; b < nruns; b += 64) {
+      const uint32_t a = sA[b];
+      sA[b] = 2 * a + sCnt[2 * b];
+      sB[b] = 2 * a + sCnt[2 * b + 1];
+    }
+    __syncthreads();
+  }
+
+  for (uint32_t b = lane; b < F; b += 64) ri.out[b] = b < nruns ? sA[b] : 0u;
+
+  // Pivot P_k (the largest key taken, i.e. the key of rank r - 1) and c_k of
+  // Eq. 2 (r minus the number of keys below P_k), for the paper's splitters.
+  if (pivots != nullptr && g.paper) {
+    const uint64_t p = row / g.sub_per_part;
+    if (row % g.sub_per_part != 0 || p == 0 || p >= g.n_parts) return;
+    if (r == 0) {  // empty prefix: c_k = 0, pivot unspecified (written as 0)
+      if (lane == 0) {
+        pivots[p - 1] = 0;
+        counts[p - 1] = 0;
+      }
+      return;
+    }
+    U best = 0;
+    for (uint32_t b = lane; b < nruns; b += 64) {
+      const uint32_t t = sA[b];
+      if (t > 0) {
+        const U k = src[ri.grp.start + (uint64_t)b * R + t - 1];
+        best = k > best ? k : best;
+      }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      const U o = __shfl_xor(best, d, 64);
+      best = o > best ? o : best;
+    }
+    uint64_t lt = 0;
+    for (uint32_t b = lane; b < nruns; b += 64) {
+      const U *run = src + ri.grp.start + (uint64_t)b * R;
+      uint32_t lo = 0, hi = run_length(glen, R, b);
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (run[mid] < best) lo = mid + 1;
+        else hi = mid;
+      }
+      lt += lo;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) lt += __shfl_xor(lt, d, 64);
+    if (lane == 0) {
+      pivots[p - 1] = unmap_runtime<U>(best, kt);
+      counts[p - 1] = r - lt;
+    }
+  }
+}
+
+// --------------------------------------------------------------- K5 -------
+struct PartInfo {
+  bool valid;
+  uint32_t size;  // keys in this partition
+  uint64_t group_start, group_len, out_off;
+  const uint32_t *lo_row, *hi_row;
+};
+
+__device__ __forceinline__ PartInfo part_info(const RunGeom &g, uint64_t pidx,
+                                              const uint32_t *table, const uint64_t *part_off) {
+  PartInfo pi;
+  pi.valid = false;
+  if (!g.paper) {
+    const uint32_t ppg = g.rows_per_group - 1;
+    const uint64_t gi = pidx / ppg, k = pidx % ppg;
+    const GroupInfo grp = group_of(g, gi);
+    const uint64_t rlo = k * g.part_len;
+    if (rlo >= grp.len) return pi;
+    const uint64_t rhi = rlo + g.part_len < grp.len ? rlo + g.part_len : grp.len;
+    pi.size = (uint32_t)(rhi - rlo);
+    pi.group_start = grp.start;
+    pi.group_len = grp.len;
+    pi.out_off = grp.start + rlo;
+    pi.lo_row = table + (gi * g.rows_per_group + k) * g.fan;
+    pi.hi_row = pi.lo_row + g.fan;
+  } else {
+    const uint64_t p = pidx / g.sub_per_part, i = pidx % g.sub_per_part;
+    const uint64_t rp = paper_rank(g, p), rp1 = paper_rank(g, p + 1);
+    const uint64_t lo = rp + i * g.part_len;
+    if (lo >= rp1) return pi;
+    const uint64_t hi = lo + g.part_len < rp1 ? lo + g.part_len : rp1;
+    pi.size = (uint32_t)(hi - lo);
+    pi.group_start = 0;
+    pi.group_len = g.n;
+    pi.out_off = part_off[p] + (lo - rp);
+    pi.lo_row = table + pidx * g.fan;
+    pi.hi_row = pi.lo_row + g.fan;
+  }
+  pi.valid = true;
+  return pi;
+}
+
+// Largest b in [0, F) with soff[b] <= pos (requires pos < soff[F]).
+__device__ __forceinline__ uint32_t find_segment(const uint32_t *soff, uint32_t F, uint32_t pos) {
+  uint32_t lo = 0, hi = F;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (soff[mid] <= pos) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int KT, bool KV, uint32_t MAXF>
+__global__ __launch_bounds__(kMergeThreads) void merge_kernel(
+    const typename Key<KT>::U *__restrict__ src, const uint32_t *__restrict__ vsrc,
+    typename Key<KT>::U *__restrict__ dst, uint32_t *__restrict__ vdst, RunGeom g,
+    const uint32_t *__restrict__ table, const uint64_t *__restrict__ part_off, int final_pass) {
+  using U = typename Key<KT>::U;
+  constexpr uint32_t P = kPart + kPart / 16;
+  __shared__ U sk[P];
+  __shared__ uint32_t sv[KV ? P : 1];
+  __shared__ uint32_t soff[MAXF + 1];
+  __shared__ uint64_t ssrc[MAXF];
+  __shared__ uint32_t wsum[kMergeThreads / 64 + 1];
+
+  const uint32_t tid = threadIdx.x;
+  const PartInfo pi = part_info(g, blockIdx.x, table, part_off);
+  if (!pi.valid) return;
+  const uint64_t R = g.run_len;
+  const uint32_t F = (uint32_t)((pi.group_len + R - 1) / R);
+
+  for (uint32_t b = tid; b < F; b += kMergeThreads) {
+    const uint32_t lo = pi.lo_row[b], hi = pi.hi_row[b];
+    const uint32_t len = run_length(pi.group_len, R, b);
+    const bool ok = lo <= hi && hi <= len;
+    if (!ok) report(kErrSplitRow);
+    soff[b] = ok ? hi - lo : (uint32_t)kPart + 1;  // forces the size check below to fail
+    ssrc[b] = pi.group_start + (uint64_t)b * R + lo;
+  }
+  __syncthreads();
+  block_exclusive_scan(soff, F, wsum);
+  const uint32_t M = soff[F];
+  if (M != pi.size) {  // split rows inconsistent with the partition: stop
+    if (tid == 0) report(kErrPartSize);
+    return;
+  }
+
+  // gather the partition's segments (coalesced within each segment)
+  {
+    uint32_t b = tid < M ? find_segment(soff, F, tid) : 0;
+#pragma unroll
+    for (int i = 0; i < kMergeItems; ++i) {
+      const uint32_t idx = i * kMergeThreads + tid;
+      if (idx < M) {
+        while (soff[b + 1] <= idx) ++b;
+        const uint64_t s = ssrc[b] + (idx - soff[b]);
+        sk[pad16(idx)] = src[s];
+        if constexpr (KV) sv[pad16(idx)] = vsrc[s];
+      }
+    }
+  }
+  __syncthreads();
+
+  // rounds of pairwise stable merges: at width w, runs of w consecutive
+  // segments are merged in pairs (the lower run wins ties)
+  const uint32_t p0 = tid * kMergeItems;
+  for (uint32_t w = 1; w < F; w <<= 1) {
+    U rk[kMergeItems];
+    uint32_t rv[KV ? kMergeItems : 1];
+    if (p0 < M) {
+      uint32_t A0 = 0, A1 = 0, B1 = 0, ai = 0, bi = 0, la = 0, lb = 0;
+      U ka = 0, kb = 0;
+      uint32_t va = 0, vb = 0;
+      auto locate = [&](uint32_t pos) {
+        const uint32_t seg = find_segment(soff, F, pos);
+        const uint32_t s0 = (seg / (2 * w)) * (2 * w);
+        A0 = soff[s0];
+        A1 = soff[s0 + w < F ? s0 + w : F];
+        B1 = soff[s0 + 2 * w < F ? s0 + 2 * w : F];
+        la = A1 - A0;
+        lb = B1 - A1;
+        const uint32_t d = pos - A0;
+        uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (sk[pad16(A0 + mid)] <= sk[pad16(A1 + d - 1 - mid)]) lo = mid + 1;
+          else hi = mid;
+        }
+        ai = lo;
+        bi = d - lo;
+        uint32_t ia = A0 + (ai < la ? ai : (la ? la - 1 : 0));
+        uint32_t ib = A1 + (bi < lb ? bi : (lb ? lb - 1 : 0));
+        ia = ia < M ? ia : M - 1;
+        ib = ib < M ? ib : M - 1;
+        ka = sk[pad16(ia)];
+        kb = sk[pad16(ib)];
+        if constexpr (KV) {
+          va = sv[pad16(ia)];
+          vb = sv[pad16(ib)];
+        }
+      };
+      locate(p0);
+#pragma unroll
+      for (int i = 0; i < kMergeItems; ++i) {
+        if (p0 + i < M) {
+          if (A0 + ai + bi == B1) locate(p0 + i);
+          const bool takeA = ai < la && (bi >= lb || ka <= kb);
+          rk[i] = takeA ? ka : kb;
+          if constexpr (KV) rv[i] = takeA ? va : vb;
+          uint32_t nxt = takeA ? A0 + ai + 1 : A1 + bi + 1;
+          nxt = nxt < M ? nxt : M - 1;
+          const U nk = sk[pad16(nxt)];
+          ka = takeA ? nk : ka;
+          kb = takeA ? kb : nk;
+          if constexpr (KV) {
+            const uint32_t nv = sv[pad16(nxt)];
+            va = takeA ? nv : va;
+            vb = takeA ? vb : nv;
+          }
+          ai += takeA ? 1u : 0u;
+          bi += takeA ? 0u : 1u;
+        }
+      }
+    }
+    __syncthreads();
+    if (p0 < M) {
+#pragma unroll
+      for (int i = 0; i < kMergeItems; ++i) {
+        if (p0 + i < M) {
+          sk[pad16(p0 + i)] = rk[i];
+          if constexpr (KV) sv[pad16(p0 + i)] = rv[i];
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < kMergeItems; ++i) {
+    const uint32_t idx = i * kMergeThreads + tid;
+    if (idx < M) {
+      const U k = sk[pad16(idx)];
+      dst[pi.out_off + idx] = final_pass ? Key<KT>::unmap(k) : k;
+      if constexpr (KV) vdst[pi.out_off + idx] = sv[pad16(idx)];
+    }
+  }
+}
+
+// --------------------------------------------------------------- K4 -------
+// Size of each paper partition (sum over blocks of its split interval) and
+// their exclusive scan: the offsets of the merged partitions in the output.
+__global__ void partition_sizes_kernel(RunGeom g, const uint32_t *__restrict__ table,
+                                       uint64_t *__restrict__ sizes) {
+  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.n_parts) return;
+  const uint32_t *lo = table + p * g.sub_per_part * g.fan;
+  const uint32_t *hi = table + (p + 1) * g.sub_per_part * g.fan;
+  uint64_t m = 0;
+  for (uint32_t b = 0; b < g.fan; ++b) m += hi[b] - lo[b];
+  sizes[p] = m;
+}
+
+__global__ __launch_bounds__(1024) void exclusive_scan_u64_kernel(const uint64_t *__restrict__ in,
+                                                                  uint64_t *__restrict__ out,
+                                                                  uint64_t n) {
+  __shared__ uint64_t wtot[16 + 1];
+  __shared__ uint64_t carry;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (uint64_t base = 0; base < n; base += 1024) {
+    const uint64_t i = base + tid;
+    const uint64_t v = i < n ? in[i] : 0;
+    uint64_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint64_t y = __shfl_up(x, d, 64);
+      if ((int)lane >= d) x += y;
+    }
+    if (lane == 63) wtot[wid] = x;
+    __syncthreads();
+    if (tid == 0) {
+      uint64_t run = 0;
+      for (int w = 0; w < 16; ++w) {
+        const uint64_t t = wtot[w];
+        wtot[w] = run;
+        run += t;
+      }
+      wtot[16] = run;
+    }
+    __syncthreads();
+    if (i < n) out[i] = carry + wtot[wid] + x - v;
+    __syncthreads();
+    if (tid == 0) carry += wtot[16];
+    __syncthreads();
+  }
+  if (tid == 0) out[n] = carry;
+}
+
+// split[b][p] = t_b at the paper's rank r_p (p = 0..n_P), as 64-bit values.
+__global__ void split_table_kernel(RunGeom g, const uint32_t *__restrict__ table,
+                                   uint64_t *__restrict__ split) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t cols = (uint64_t)g.n_parts + 1;
+  if (i >= (uint64_t)g.fan * cols) return;
+  const uint64_t b = i / cols, p = i % cols;
+  split[i] = table[p * g.sub_per_part * g.fan + b];
+}
+
+template <int KT>
+__global__ void unmap_copy_kernel(const typename Key<KT>::U *__restrict__ src,
+                                  typename Key<KT>::U *__restrict__ dst, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = Key<KT>::unmap(src[i]);
+}
+
+template <typename F>
+hipError_t dispatch_kt(int kt, F &&f) {
+  switch (kt) {
+    case 0: return f(std::integral_constant<int, 0>{});
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 3: return f(std::integral_constant<int, 3>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 5: return f(std::integral_constant<int, 5>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers ---
+hipError_t launch_tile_sort(int kt, bool kv, const void *in, const uint32_t *vin, void *out,
+                            uint32_t *vout, uint64_t n, uint64_t seg_len, int final_pass,
+                            hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint64_t tps = (seg_len + kTile - 1) / kTile;
+  const uint64_t nseg = (n + seg_len - 1) / seg_len;
+  const uint64_t grid = nseg * tps;
+  return dispatch_kt(kt, [&](auto ktc) {
+    constexpr int KT = decltype(ktc)::value;
+    using U = typename Key<KT>::U;
+    if (kv)
+      hipLaunchKernelGGL((tile_sort_kernel<KT, true>), dim3((uint32_t)grid), dim3(kTileThreads), 0, s,
+                         (const U *)in, vin, (U *)out, vout, n, seg_len, tps, final_pass);
+    else
+      hipLaunchKernelGGL((tile_sort_kernel<KT, false>), dim3((uint32_t)grid), dim3(kTileThreads), 0, s,
+                         (const U *)in, vin, (U *)out, vout, n, seg_len, tps, final_pass);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_corank(int kt, const void *src, const RunGeom &g, uint32_t *table,
+                         void *pivots, uint64_t *counts, hipStream_t s) {
+  const uint64_t rows = g.total_rows();
+  if (rows == 0) return hipSuccess;
+  auto go = [&](auto u, auto maxf) -> hipError_t {
+    using U = decltype(u);
+    constexpr uint32_t MAXF = decltype(maxf)::value;
+    hipLaunchKernelGGL((corank_kernel<U, MAXF>), dim3((uint32_t)rows), dim3(kCorankThreads), 0, s,
+                       (const U *)src, g, table, (U *)pivots, counts, kt);
+    return hipGetLastError();
+  };
+  const bool wide = key_bytes(kt) == 8;
+  if (g.fan <= 64)
+    return wide ? go(uint64_t{}, std::integral_constant<uint32_t, 64>{})
+                : go(uint32_t{}, std::integral_constant<uint32_t, 64>{});
+  if (g.fan <= 512)
+    return wide ? go(uint64_t{}, std::integral_constant<uint32_t, 512>{})
+                : go(uint32_t{}, std::integral_constant<uint32_t, 512>{});
+  if (g.fan <= kMaxRuns)
+    return wide ? go(uint64_t{}, std::integral_constant<uint32_t, kMaxRuns>{})
+                : go(uint32_t{}, std::integral_constant<uint32_t, kMaxRuns>{});
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_merge(int kt, bool kv, const void *src, const uint32_t *vsrc, void *dst,
+                        uint32_t *vdst, const RunGeom &g, const uint32_t *table,
+                        const uint64_t *part_offsets, int final_pass, hipStream_t s) {
+  const uint64_t parts = g.total_parts();
+  if (parts == 0) return hipSuccess;
+  return dispatch_kt(kt, [&](auto ktc) {
+    constexpr int KT = decltype(ktc)::value;
+    using U = typename Key<KT>::U;
+    auto go = [&](auto kvc, auto maxf) -> hipError_t {
+      constexpr bool KV = decltype(kvc)::value;
+      constexpr uint32_t MAXF = decltype(maxf)::value;
+      hipLaunchKernelGGL((merge_kernel<KT, KV, MAXF>), dim3((uint32_t)parts), dim3(kMergeThreads), 0, s,
+                         (const U *)src, vsrc, (U *)dst, vdst, g, table, part_offsets, final_pass);
+      return hipGetLastError();
+    };
+    if (g.fan <= 64)
+      return kv ? go(std::true_type{}, std::integral_constant<uint32_t, 64>{})
+                : go(std::false_type{}, std::integral_constant<uint32_t, 64>{});
+    if (g.fan <= kMaxRuns)
+      return kv ? go(std::true_type{}, std::integral_constant<uint32_t, kMaxRuns>{})
+                : go(std::false_type{}, std::integral_constant<uint32_t, kMaxRuns>{});
+    return hipErrorInvalidValue;
+  });
+}
+
+hipError_t launch_partition_offsets(const RunGeom &g, const uint32_t *table, uint64_t *sizes,
+                                    uint64_t *offsets, hipStream_t s) {
+  const uint32_t blocks = (uint32_t)((g.n_parts + 255) / 256);
+  hipLaunchKernelGGL(partition_sizes_kernel, dim3(blocks), dim3(256), 0, s, g, table, sizes);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(exclusive_scan_u64_kernel, dim3(1), dim3(1024), 0, s, (const uint64_t *)sizes,
+                     offsets, (uint64_t)g.n_parts);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_table(const RunGeom &g, const uint32_t *table, uint64_t *split,
+                              hipStream_t s) {
+  const uint64_t total = (uint64_t)g.fan * ((uint64_t)g.n_parts + 1);
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(split_table_kernel, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, g,
+                     table, split);
+  return hipGetLastError();
+}
+
+hipError_t read_device_error(uint32_t *code, bool clear) {
+  hipError_t e = hipMemcpyFromSymbol(code, HIP_SYMBOL(g_device_error), sizeof(uint32_t), 0,
+                                     hipMemcpyDeviceToHost);
+  if (e != hipSuccess || !clear) return e;
+  const uint32_t zero = 0;
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_device_error), &zero, sizeof(uint32_t), 0,
+                           hipMemcpyHostToDevice);
+}
+
+hipError_t launch_unmap_copy(int kt, const void *src, void *dst, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  return dispatch_kt(kt, [&](auto ktc) {
+    constexpr int KT = decltype(ktc)::value;
+    using U = typename Key<KT>::U;
+    hipLaunchKernelGGL((unmap_copy_kernel<KT>), dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s,
+                       (const U *)src, (U *)dst, n);
+    return hipGetLastError();
+  });
+}
+
+}  // namespace pss

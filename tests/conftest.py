@@ -19,3 +19,14 @@ def oracle_lib():
 
     oracle.build()
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _device_error_word(request):
+    """After every GPU test, the library's device error word must be clear."""
+    yield
+    if request.node.get_closest_marker("gpu") is None:
+        return
+    import paper_2305_05245_amd as pss
+
+    assert pss.device_check(0) == 0, "a kernel reported a broken invariant"

@@ -1,0 +1,116 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/*.h, and its host-side argument checks, workspace sizes and
+launch plans behave as documented."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2305_05245_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(pss_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def test_status_strings(lib):
+    assert _lib.status_string(_lib.OK) == "PSS_OK"
+    assert _lib.status_string(_lib.ERR_WORKSPACE) == "PSS_ERR_WORKSPACE"
+
+
+A, B, C, D = 0x10000, 0x20000000, 0x40000000, 0x60000000   # disjoint fake addresses
+
+
+@pytest.mark.parametrize("case,expect", [
+    (dict(key=9), _lib.ERR_INVALID),
+    (dict(val=7), _lib.ERR_INVALID),
+    (dict(n_blocks=4, n_parts=0), _lib.ERR_INVALID),
+    (dict(n_blocks=0, n_parts=3), _lib.ERR_INVALID),
+    (dict(keys_in=0), _lib.ERR_INVALID),
+    (dict(keys_out=0), _lib.ERR_INVALID),
+    (dict(keys_out=A + 8), _lib.ERR_INVALID),          # overlaps keys_in
+    (dict(keys_out=A), _lib.ERR_INVALID),              # in == out
+    (dict(val=1, vals_in=0), _lib.ERR_INVALID),
+    (dict(val=1, vals_out=C + 4), _lib.ERR_INVALID),   # vals overlap
+    (dict(val=1, vals_out=B), _lib.ERR_INVALID),       # vals_out on keys_out
+    (dict(n=1 << 31), _lib.ERR_UNSUPPORTED),
+    (dict(n_blocks=4096, n_parts=2), _lib.ERR_UNSUPPORTED),
+    (dict(n_blocks=2, n_parts=(1 << 22) + 1), _lib.ERR_UNSUPPORTED),
+    (dict(n_blocks=2048, n_parts=1 << 20), _lib.ERR_UNSUPPORTED),   # split table too large
+    (dict(ws_bytes=16), _lib.ERR_WORKSPACE),
+    (dict(), _lib.OK),
+    (dict(val=1), _lib.OK),
+    (dict(n=0, keys_in=0, keys_out=0), _lib.OK),
+    (dict(n_blocks=64, n_parts=64), _lib.OK),
+])
+def test_validate(lib, case, expect):
+    args = dict(key=_lib.I64, val=0, keys_in=A, keys_out=B, vals_in=C, vals_out=D, n=1000,
+                n_blocks=0, n_parts=0, ws_bytes=None)
+    args.update(case)
+    assert _lib.validate(**args) == expect, _lib.last_error()
+
+
+def test_sort_without_context_is_rejected(lib):
+    st = lib.pss_sort(None, _lib.I64, 0, A, B, None, None, 10, 0, 0, C, 1 << 20, None)
+    assert st == _lib.ERR_INVALID
+    assert "context" in _lib.last_error()
+
+
+def test_workspace_bytes_grow_with_n(lib):
+    a = _lib.workspace_bytes(_lib.I64, 0, 1 << 20)
+    b = _lib.workspace_bytes(_lib.I64, 0, 1 << 22)
+    assert a >= (1 << 20) * 8 and b >= (1 << 22) * 8 and b > a
+    kv = _lib.workspace_bytes(_lib.U64, 1, 1 << 20)
+    assert kv >= a + (1 << 20) * 4
+    paper = _lib.workspace_bytes(_lib.I32, 0, 1 << 20, 64, 64)
+    assert paper >= 2 * (1 << 20) * 4
+    assert _lib.workspace_bytes(_lib.I64, 0, 0) == 0
+
+
+@pytest.mark.parametrize("n,passes", [
+    (1, []), (8192, []), (8193, [2]), (1 << 20, [128 // 16 * 16 // 8, 8]),
+    (1 << 28, [32, 32, 32]), (1 << 27, [32, 32, 16]),
+])
+def test_auto_plan(lib, n, passes):
+    p = _lib.plan(_lib.I64, 0, n)
+    assert p["mode"] == "auto" and p["tile"] == 8192
+    if n == 1 << 20:
+        assert p["passes"] == [16, 8]
+    else:
+        assert p["passes"] == passes
+    # product of fan-ins covers every tile
+    prod = 1
+    for f in p["passes"]:
+        prod *= f
+    assert prod * p["tile"] >= n
+    assert p["hbm_passes"] == 1 + len(p["passes"])
+
+
+def test_paper_plan(lib):
+    p = _lib.plan(_lib.I32, 0, 1 << 20, 64, 64)
+    assert p["mode"] == "paper" and p["n_blocks"] == 64 and p["n_parts"] == 64
+    assert p["block_passes"] == [2]          # blocks of 16384 keys = 2 tiles
+    assert p["hbm_passes"] == 3

@@ -68,7 +68,7 @@ def swapped_i64(n: int, seed: int = 6, fraction: float = 0.01) -> np.ndarray:
     return a
 
 
-def _apply_transpositions(a: np.ndarray, i: np.ndarray, j: np.ndarray, chunk: int = 1 << 16):
+def _apply_transpositions(a: np.ndarray, i: np.ndarray, j: np.ndarray, chunk: int = 1 << 12):
     # Transpositions are applied strictly in order.  A chunk whose position
     # pairs touch no position twice can be applied at once; others fall back to
     # a plain loop.

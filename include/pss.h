@@ -158,6 +158,19 @@ pss_status pss_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, uint6
                          size_t ws_bytes, void *stream);
 
 /*
+ * Per-launch timing for measurement.  While enabled, every kernel launch that
+ * a call on ctx makes is bracketed by two HIP events recorded on that call's
+ * stream (a few microseconds of overhead per launch).  pss_profile_read waits
+ * for the recorded events and writes a NUL-terminated JSON object to buf (host
+ * memory): {"<kernel family>": {"launches": L, "ms": total milliseconds,
+ * "bytes": algorithmic HBM bytes of those launches}, ...}, then forgets the
+ * records.  Families: tile_sort (step 1), split_search (steps 2-3), merge
+ * (step 4), offset_scan (offsets of the merged partitions).
+ */
+pss_status pss_profile_enable(pss_ctx *ctx, int on);
+pss_status pss_profile_read(pss_ctx *ctx, char *buf, size_t buf_len);
+
+/*
  * Wait for all work on ctx's device, then read and clear the library's device
  * error word into *code (host memory): 0 when every kernel found its
  * invariants intact.  Bits: 1 = splitter candidate set overflow, 2 = splitter

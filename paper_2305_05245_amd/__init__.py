@@ -109,6 +109,17 @@ def sort(keys: torch.Tensor, vals: torch.Tensor | None = None, n_blocks: int = 0
     return out, (vals_out if vals is not None else None)
 
 
+def profile(on: bool, device: int = 0) -> None:
+    """Turn per-launch event timing of the library on or off."""
+    _context(device).profile(on)
+
+
+def profile_read(device: int = 0) -> dict:
+    """Per kernel family: launches, total ms and algorithmic bytes since the
+    last read (waits for the recorded events)."""
+    return _context(device).profile_read()
+
+
 def device_check(device: int = 0) -> int:
     """Synchronise `device` and return (and clear) the library's device error
     word: 0 when every kernel found its invariants intact."""

@@ -35,6 +35,8 @@ SIGNATURES = {
     "pss_plan_describe": (_int, [_int, _int, _u64, _u32, _u32, _c.c_char_p, _sz]),
     "pss_sort": (_int, [_vp, _int, _int, _vp, _vp, _vp, _vp, _u64, _u32, _u32, _vp, _sz, _vp]),
     "pss_device_check": (_int, [_vp, _c.POINTER(_u32)]),
+    "pss_profile_enable": (_int, [_vp, _int]),
+    "pss_profile_read": (_int, [_vp, _c.c_char_p, _sz]),
     "pss_splitters": (_int, [_vp, _int, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                              _vp]),
 }
@@ -126,6 +128,14 @@ class Context:
         check(self.lib.pss_sort(self.handle, key, val, keys_in or None, keys_out or None,
                                 vals_in or None, vals_out or None, n, n_blocks, n_parts,
                                 ws or None, ws_bytes, stream or None), self.handle)
+
+    def profile(self, on: bool) -> None:
+        check(self.lib.pss_profile_enable(self.handle, 1 if on else 0), self.handle)
+
+    def profile_read(self) -> dict:
+        buf = ctypes.create_string_buffer(1 << 16)
+        check(self.lib.pss_profile_read(self.handle, buf, len(buf)), self.handle)
+        return json.loads(buf.value.decode())
 
     def device_check(self) -> int:
         """Synchronise the device and return (and clear) the error word."""

@@ -11,9 +11,18 @@
 #include "../../include/pss.h"
 #include "pss_internal.hpp"
 
+struct pss_prof_rec {
+  const char *name;   // kernel family
+  hipEvent_t begin, end;
+  uint64_t bytes;     // algorithmic HBM bytes of this launch
+};
+
 struct pss_ctx {
   int device = 0;
   std::string last_error;
+  bool profiling = false;
+  std::vector<pss_prof_rec> recs;
+  std::vector<hipEvent_t> pool;  // events ready for reuse
 };
 
 namespace {
@@ -189,21 +198,70 @@ pss_status validate(const pss_ctx *ctx, pss_key_t key, pss_val_t val, const void
     if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
   } while (0)
 
+// Optional per-launch timing: when profiling is on, every kernel launch is
+// bracketed by two events recorded on the launch stream.
+hipEvent_t take_event(pss_ctx *ctx) {
+  if (!ctx->pool.empty()) {
+    hipEvent_t e = ctx->pool.back();
+    ctx->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct LaunchTimer {
+  pss_ctx *ctx;
+  hipStream_t s;
+  pss_prof_rec rec{};
+  bool on;
+  LaunchTimer(pss_ctx *c, const char *name, uint64_t bytes, hipStream_t st)
+      : ctx(c), s(st), on(c && c->profiling) {
+    if (!on) return;
+    rec.name = name;
+    rec.bytes = bytes;
+    rec.begin = take_event(ctx);
+    rec.end = take_event(ctx);
+    if (!rec.begin || !rec.end) {
+      on = false;
+      return;
+    }
+    hipEventRecord(rec.begin, s);
+  }
+  ~LaunchTimer() {
+    if (!on) return;
+    hipEventRecord(rec.end, s);
+    ctx->recs.push_back(rec);
+  }
+};
+
 // Tile sort plus the merge passes of every segment.  bufs[q] receives the
 // output of pass q (bufs[0] the tile sort); values likewise.
 pss_status run_segment_sort(pss_ctx *ctx, const Plan &p, int kt, const void *keys_in,
                             const uint32_t *vals_in, void *const *kbuf, uint32_t *const *vbuf,
                             int final_last, uint32_t *table, hipStream_t s) {
   const size_t P = p.passes.size();
-  PSS_TRY(pss::launch_tile_sort(kt, p.kv, keys_in, vals_in, kbuf[0], vbuf[0], p.n, p.seg_len,
-                                final_last && P == 0, s),
-          "tile sort launch");
+  const uint64_t sweep = 2 * p.n * ((uint64_t)p.kb + (p.kv ? 4 : 0));  // read + write all
+  {
+    LaunchTimer t(ctx, "tile_sort", sweep, s);
+    PSS_TRY(pss::launch_tile_sort(kt, p.kv, keys_in, vals_in, kbuf[0], vbuf[0], p.n, p.seg_len,
+                                  final_last && P == 0, s),
+            "tile sort launch");
+  }
   for (size_t q = 1; q <= P; ++q) {
     const pss::RunGeom &g = p.passes[q - 1];
-    PSS_TRY(pss::launch_corank(kt, kbuf[q - 1], g, table, nullptr, nullptr, s), "split search launch");
-    PSS_TRY(pss::launch_merge(kt, p.kv, kbuf[q - 1], vbuf[q - 1], kbuf[q], vbuf[q], g, table, nullptr,
-                              final_last && q == P, s),
-            "merge launch");
+    {
+      LaunchTimer t(ctx, "split_search", g.total_rows() * g.fan * 4, s);
+      PSS_TRY(pss::launch_corank(kt, kbuf[q - 1], g, table, nullptr, nullptr, s),
+              "split search launch");
+    }
+    {
+      LaunchTimer t(ctx, "merge", sweep, s);
+      PSS_TRY(pss::launch_merge(kt, p.kv, kbuf[q - 1], vbuf[q - 1], kbuf[q], vbuf[q], g, table,
+                                nullptr, final_last && q == P, s),
+              "merge launch");
+    }
   }
   return PSS_OK;
 }
@@ -228,7 +286,61 @@ pss_status pss_create(int device, pss_ctx **out) {
   return PSS_OK;
 }
 
-void pss_destroy(pss_ctx *ctx) { delete ctx; }
+void pss_destroy(pss_ctx *ctx) {
+  if (!ctx) return;
+  for (auto &r : ctx->recs) {
+    hipEventDestroy(r.begin);
+    hipEventDestroy(r.end);
+  }
+  for (auto e : ctx->pool) hipEventDestroy(e);
+  delete ctx;
+}
+
+pss_status pss_profile_enable(pss_ctx *ctx, int on) {
+  if (!ctx) return fail(nullptr, PSS_ERR_INVALID, "null context");
+  ctx->profiling = on != 0;
+  return PSS_OK;
+}
+
+pss_status pss_profile_read(pss_ctx *ctx, char *buf, size_t buf_len) {
+  if (!ctx || !buf || buf_len == 0) return fail(ctx, PSS_ERR_INVALID, "null argument");
+  struct Agg {
+    std::string name;
+    uint64_t launches = 0, bytes = 0;
+    double ms = 0;
+  };
+  std::vector<Agg> agg;
+  for (auto &r : ctx->recs) {
+    PSS_TRY(hipEventSynchronize(r.end), "hipEventSynchronize");
+    float ms = 0;
+    PSS_TRY(hipEventElapsedTime(&ms, r.begin, r.end), "hipEventElapsedTime");
+    auto it = std::find_if(agg.begin(), agg.end(), [&](const Agg &a) { return a.name == r.name; });
+    if (it == agg.end()) {
+      agg.push_back(Agg{r.name});
+      it = agg.end() - 1;
+    }
+    it->launches++;
+    it->bytes += r.bytes;
+    it->ms += ms;
+  }
+  std::string j = "{";
+  for (size_t i = 0; i < agg.size(); ++i) {
+    char item[256];
+    snprintf(item, sizeof item, "%s\"%s\": {\"launches\": %llu, \"ms\": %.6f, \"bytes\": %llu}",
+             i ? ", " : "", agg[i].name.c_str(), (unsigned long long)agg[i].launches, agg[i].ms,
+             (unsigned long long)agg[i].bytes);
+    j += item;
+  }
+  j += "}";
+  if (j.size() + 1 > buf_len) return fail(ctx, PSS_ERR_INVALID, "buffer too small");
+  memcpy(buf, j.c_str(), j.size() + 1);
+  for (auto &r : ctx->recs) {
+    ctx->pool.push_back(r.begin);
+    ctx->pool.push_back(r.end);
+  }
+  ctx->recs.clear();
+  return PSS_OK;
+}
 
 const char *pss_status_string(pss_status s) {
   switch (s) {
@@ -340,10 +452,21 @@ pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys
     if (st != PSS_OK) return st;
     uint64_t *sizes = (uint64_t *)(w + p.off_sizes);
     uint64_t *offsets = (uint64_t *)(w + p.off_offsets);
-    PSS_TRY(pss::launch_corank(kt, kb[P], p.top, table, nullptr, nullptr, s), "splitter launch");
-    PSS_TRY(pss::launch_partition_offsets(p.top, table, sizes, offsets, s), "offset scan launch");
-    PSS_TRY(pss::launch_merge(kt, p.kv, kb[P], vb[P], keys_out, vals_out, p.top, table, offsets, 1, s),
-            "merge launch");
+    const uint64_t sweep = 2 * p.n * ((uint64_t)p.kb + (p.kv ? 4 : 0));
+    {
+      LaunchTimer t(ctx, "split_search", p.top.total_rows() * p.top.fan * 4, s);
+      PSS_TRY(pss::launch_corank(kt, kb[P], p.top, table, nullptr, nullptr, s), "splitter launch");
+    }
+    {
+      LaunchTimer t(ctx, "offset_scan", (uint64_t)p.top.n_parts * 16, s);
+      PSS_TRY(pss::launch_partition_offsets(p.top, table, sizes, offsets, s), "offset scan launch");
+    }
+    {
+      LaunchTimer t(ctx, "merge", sweep, s);
+      PSS_TRY(pss::launch_merge(kt, p.kv, kb[P], vb[P], keys_out, vals_out, p.top, table, offsets, 1,
+                                s),
+              "merge launch");
+    }
   }
   return PSS_OK;
 }

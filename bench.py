@@ -92,6 +92,9 @@ def main() -> int:
     ap.add_argument("--all-dists", action="store_true",
                     help="also time the other four int64 distributions")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only time a plain device-to-device copy of the keys (bandwidth and "
+                         "counter calibration), print its line and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -118,6 +121,22 @@ def main() -> int:
     ws = torch.empty(_lib.workspace_bytes(_lib.I64, _lib.VAL_NONE, n), dtype=torch.uint8,
                      device="cuda")
     plan = _lib.plan(_lib.I64, _lib.VAL_NONE, n)
+
+    # plain copy of the same bytes: the achievable read+write bandwidth here
+    for _ in range(2):
+        out.copy_(keys_dev)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out.copy_(keys_dev)
+    torch.cuda.synchronize()
+    copy_s = (time.perf_counter() - t0) / reps
+    copy_gbs = 2 * 8 * n / copy_s / 1e9
+    if args.copy_only:
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n,
+                          "copy_ms": round(copy_s * 1e3, 4), "copy_gbs": round(copy_gbs, 1)}))
+        return 0
 
     wall, ev_s, kernels = time_sort(pss, torch, keys_dev, out, ws, args.steps, args.warmup,
                                     profile=True)
@@ -166,6 +185,7 @@ def main() -> int:
         "roofline": roofline,
         "sort_roofline_2pass_frac": round(algo_bytes / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
         "hip_event_ms_per_step": round(ev_s / args.steps * 1e3, 4),
+        "copy_gbs": round(copy_gbs, 1),
         "kernels": {k: {"launches": v["launches"] // args.steps,
                         "ms_per_step": round(v["ms"] / args.steps, 4)} for k, v in kernels.items()},
     }

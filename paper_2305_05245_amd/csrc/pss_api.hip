@@ -88,9 +88,13 @@ struct Plan {
   std::vector<pss::RunGeom> passes;   // merge passes inside each segment
   pss::RunGeom top{};                 // paper mode: the cross-block merge
   uint64_t table_entries = 0;
+  // merged-sample index used by the splitter search of every segment pass
+  uint64_t n_samples = 0, sample_table_entries = 0, prefix_entries = 0;
   // workspace layout (byte offsets)
   size_t off_keys0 = 0, off_keys1 = 0, off_vals0 = 0, off_vals1 = 0;
-  size_t off_table = 0, off_sizes = 0, off_offsets = 0, total = 0;
+  size_t off_table = 0, off_sizes = 0, off_offsets = 0;
+  size_t off_samples = 0, off_skeys = 0, off_sruns = 0, off_stable = 0, off_prefix = 0;
+  size_t total = 0;
 };
 
 pss_status make_plan(pss_key_t key, pss_val_t val, uint64_t n, uint32_t n_blocks,
@@ -126,8 +130,15 @@ pss_status make_plan(pss_key_t key, pss_val_t val, uint64_t n, uint32_t n_blocks
     }
     p->table_entries = entries;
   }
-  for (const auto &g : p->passes)
+  for (const auto &g : p->passes) {
     p->table_entries = std::max<uint64_t>(p->table_entries, g.total_rows() * (uint64_t)g.fan);
+    const pss::RunGeom gs = pss::sample_geom(g);
+    p->n_samples = std::max<uint64_t>(p->n_samples, gs.n);
+    p->sample_table_entries =
+        std::max<uint64_t>(p->sample_table_entries, gs.total_rows() * (uint64_t)gs.fan);
+    p->prefix_entries = std::max<uint64_t>(
+        p->prefix_entries, gs.total_parts() * (uint64_t)(pss::kPart / pss::kChunk) * gs.fan);
+  }
 
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -142,6 +153,13 @@ pss_status make_plan(pss_key_t key, pss_val_t val, uint64_t n, uint32_t n_blocks
     p->off_vals1 = p->paper ? take(n * sizeof(uint32_t)) : 0;
   }
   p->off_table = take(p->table_entries * sizeof(uint32_t));
+  if (!p->passes.empty()) {
+    p->off_samples = take(p->n_samples * (size_t)p->kb);
+    p->off_skeys = take(p->n_samples * (size_t)p->kb);
+    p->off_sruns = take(p->n_samples * sizeof(uint32_t));
+    p->off_stable = take(p->sample_table_entries * sizeof(uint32_t));
+    p->off_prefix = take(p->prefix_entries * sizeof(uint32_t));
+  }
   if (p->paper) {
     p->off_sizes = take((size_t)n_parts * sizeof(uint64_t));
     p->off_offsets = take(((size_t)n_parts + 1) * sizeof(uint64_t));
@@ -237,29 +255,52 @@ struct LaunchTimer {
 };
 
 // Tile sort plus the merge passes of every segment.  bufs[q] receives the
-// output of pass q (bufs[0] the tile sort); values likewise.
+// output of pass q (bufs[0] the tile sort); values likewise.  Each pass first
+// merges the regular samples its input runs left (a 1/kSample-size merge that
+// records run ids and per-run prefix counts), then searches the exact
+// splitters starting from those samples, then merges the data.
 pss_status run_segment_sort(pss_ctx *ctx, const Plan &p, int kt, const void *keys_in,
                             const uint32_t *vals_in, void *const *kbuf, uint32_t *const *vbuf,
-                            int final_last, uint32_t *table, hipStream_t s) {
+                            int final_last, char *w, hipStream_t s) {
   const size_t P = p.passes.size();
   const uint64_t sweep = 2 * p.n * ((uint64_t)p.kb + (p.kv ? 4 : 0));  // read + write all
+  uint32_t *table = (uint32_t *)(w + p.off_table);
+  void *samples = P ? (void *)(w + p.off_samples) : nullptr;
+  void *skeys = w + p.off_skeys;
+  uint32_t *sruns = (uint32_t *)(w + p.off_sruns);
+  uint32_t *stable = (uint32_t *)(w + p.off_stable);
+  uint32_t *prefix = (uint32_t *)(w + p.off_prefix);
   {
     LaunchTimer t(ctx, "tile_sort", sweep, s);
     PSS_TRY(pss::launch_tile_sort(kt, p.kv, keys_in, vals_in, kbuf[0], vbuf[0], p.n, p.seg_len,
-                                  final_last && P == 0, s),
+                                  final_last && P == 0, samples, s),
             "tile sort launch");
   }
   for (size_t q = 1; q <= P; ++q) {
     const pss::RunGeom &g = p.passes[q - 1];
+    const pss::RunGeom gs = pss::sample_geom(g);
+    const uint64_t sbytes = gs.n * (uint64_t)p.kb;
+    {
+      LaunchTimer t(ctx, "sample_split_search", gs.total_rows() * gs.fan * 4, s);
+      PSS_TRY(pss::launch_corank(kt, samples, gs, stable, nullptr, nullptr, s),
+              "sample split search launch");
+    }
+    {
+      LaunchTimer t(ctx, "sample_merge", 2 * sbytes + gs.n * 4, s);
+      PSS_TRY(pss::launch_merge(kt, 2, samples, nullptr, skeys, sruns, gs, stable, nullptr, 0,
+                                nullptr, prefix, s),
+              "sample merge launch");
+    }
     {
       LaunchTimer t(ctx, "split_search", g.total_rows() * g.fan * 4, s);
-      PSS_TRY(pss::launch_corank(kt, kbuf[q - 1], g, table, nullptr, nullptr, s),
+      PSS_TRY(pss::launch_corank_sampled(kt, kbuf[q - 1], g, table, sruns, prefix, s),
               "split search launch");
     }
     {
       LaunchTimer t(ctx, "merge", sweep, s);
-      PSS_TRY(pss::launch_merge(kt, p.kv, kbuf[q - 1], vbuf[q - 1], kbuf[q], vbuf[q], g, table,
-                                nullptr, final_last && q == P, s),
+      PSS_TRY(pss::launch_merge(kt, p.kv ? 1 : 0, kbuf[q - 1], vbuf[q - 1], kbuf[q], vbuf[q], g,
+                                table, nullptr, final_last && q == P, q < P ? samples : nullptr,
+                                nullptr, s),
               "merge launch");
     }
   }
@@ -437,7 +478,7 @@ pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys
       kb[q] = to_out ? keys_out : (void *)(w + p.off_keys0);
       if (p.kv) vb[q] = to_out ? vals_out : (uint32_t *)(w + p.off_vals0);
     }
-    st = run_segment_sort(ctx, p, kt, keys_in, vals_in, kb.data(), vb.data(), 1, table, s);
+    st = run_segment_sort(ctx, p, kt, keys_in, vals_in, kb.data(), vb.data(), 1, w, s);
     if (st != PSS_OK) return st;
   } else {
     // block sort ends in workspace buffer 0; the cross-block merge writes out
@@ -448,7 +489,7 @@ pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys
       kb[q] = even ? (void *)(w + p.off_keys0) : (void *)(w + p.off_keys1);
       if (p.kv) vb[q] = even ? (uint32_t *)(w + p.off_vals0) : (uint32_t *)(w + p.off_vals1);
     }
-    st = run_segment_sort(ctx, p, kt, keys_in, vals_in, kb.data(), vb.data(), 0, table, s);
+    st = run_segment_sort(ctx, p, kt, keys_in, vals_in, kb.data(), vb.data(), 0, w, s);
     if (st != PSS_OK) return st;
     uint64_t *sizes = (uint64_t *)(w + p.off_sizes);
     uint64_t *offsets = (uint64_t *)(w + p.off_offsets);
@@ -463,8 +504,8 @@ pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys
     }
     {
       LaunchTimer t(ctx, "merge", sweep, s);
-      PSS_TRY(pss::launch_merge(kt, p.kv, kb[P], vb[P], keys_out, vals_out, p.top, table, offsets, 1,
-                                s),
+      PSS_TRY(pss::launch_merge(kt, p.kv ? 1 : 0, kb[P], vb[P], keys_out, vals_out, p.top, table,
+                                offsets, 1, nullptr, nullptr, s),
               "merge launch");
     }
   }
@@ -517,7 +558,7 @@ pss_status pss_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, uint6
     const bool even = ((P - q) % 2) == 0;
     kb[q] = even ? (void *)(w + p.off_keys0) : (void *)(w + p.off_keys1);
   }
-  st = run_segment_sort(ctx, p, kt, keys_in, nullptr, kb.data(), vb.data(), 0, table, s);
+  st = run_segment_sort(ctx, p, kt, keys_in, nullptr, kb.data(), vb.data(), 0, w, s);
   if (st != PSS_OK) return st;
   uint64_t *sizes = (uint64_t *)(w + p.off_sizes);
   uint64_t *offs = (uint64_t *)(w + p.off_offsets);

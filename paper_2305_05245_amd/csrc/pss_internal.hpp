@@ -26,6 +26,16 @@ constexpr uint32_t kMaxRuns = 2048;
 // Runs merged by one pass of the automatic plan (powers of two).
 constexpr int kMaxFanLog2 = 5;
 
+// Every sorted run also leaves a regular sample: the keys at run positions
+// kSample*i + kSample-1.  A pass merges the samples first and reads the top
+// levels of every splitter search off the merged samples.
+constexpr int kSampleLog2 = 5;
+constexpr uint32_t kSample = 1u << kSampleLog2;
+// Merged samples carry per-run prefix counts every kChunk entries.
+constexpr uint32_t kChunk = 64;
+// Largest fan-in for which the sampled search is used.
+constexpr uint32_t kMaxSampledFan = 32;
+
 // Geometry of one merge pass.  The array is cut into uniform segments of
 // seg_len keys (the last one short); inside a segment, sorted runs of run_len
 // keys are merged in groups of `fan` runs, each group's output cut into
@@ -66,14 +76,26 @@ hipError_t read_device_error(uint32_t *code, bool clear);
 // key-type codes (same numbering as pss_key_t)
 inline int key_bytes(int kt) { return (kt == 0 || kt == 1 || kt == 4) ? 4 : 8; }
 
+// Geometry of the sample array of the runs described by g (same groups).
+RunGeom sample_geom(const RunGeom &g);
+
+// samples: optional output, every kSample-th key of each sorted tile.
 hipError_t launch_tile_sort(int kt, bool kv, const void *in, const uint32_t *vin, void *out,
                             uint32_t *vout, uint64_t n, uint64_t seg_len, int final_pass,
-                            hipStream_t s);
+                            void *samples, hipStream_t s);
 hipError_t launch_corank(int kt, const void *src, const RunGeom &g, uint32_t *table,
                          void *pivots, uint64_t *counts, hipStream_t s);
-hipError_t launch_merge(int kt, bool kv, const void *src, const uint32_t *vsrc, void *dst,
+// Splitter search that starts from the merged samples (see merge mode 2).
+hipError_t launch_corank_sampled(int kt, const void *src, const RunGeom &g, uint32_t *table,
+                                 const uint32_t *sample_runs, const uint32_t *sample_prefix,
+                                 hipStream_t s);
+// vmode 0: keys only; 1: keys + uint32 payload; 2: merge of a sample array,
+// payload = source run index, per-run prefix counts written to `prefix`.
+// samples: optional output, every kSample-th key of each output run.
+hipError_t launch_merge(int kt, int vmode, const void *src, const uint32_t *vsrc, void *dst,
                         uint32_t *vdst, const RunGeom &g, const uint32_t *table,
-                        const uint64_t *part_offsets, int final_pass, hipStream_t s);
+                        const uint64_t *part_offsets, int final_pass, void *samples,
+                        uint32_t *prefix, hipStream_t s);
 hipError_t launch_partition_offsets(const RunGeom &g, const uint32_t *table, uint64_t *sizes,
                                     uint64_t *offsets, hipStream_t s);
 hipError_t launch_split_table(const RunGeom &g, const uint32_t *table, uint64_t *split,

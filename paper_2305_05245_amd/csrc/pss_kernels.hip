@@ -168,7 +168,7 @@ template <int KT, bool KV>
 __global__ __launch_bounds__(kTileThreads) void tile_sort_kernel(
     const typename Key<KT>::U *__restrict__ in, const uint32_t *__restrict__ vin,
     typename Key<KT>::U *__restrict__ out, uint32_t *__restrict__ vout, uint64_t n,
-    uint64_t seg_len, uint64_t tiles_per_seg, int final_pass) {
+    uint64_t seg_len, uint64_t tiles_per_seg, int final_pass, typename Key<KT>::U *__restrict__ samples) {
   using U = typename Key<KT>::U;
   constexpr uint32_t P = kTile + kTile / 16;
   __shared__ U sk[P];
@@ -271,6 +271,13 @@ __global__ __launch_bounds__(kTileThreads) void tile_sort_kernel(
       out[start + idx] = final_pass ? Key<KT>::unmap(k) : k;
       if constexpr (KV) vout[start + idx] = sv[pad16(idx)];
     }
+  }
+  // regular samples of the sorted tile (every kSample-th key, tile positions
+  // kSample*i + kSample-1) for the next level's splitter search
+  if (samples != nullptr) {
+    const uint64_t sbase = seg * (seg_len >> kSampleLog2) + ((j * (uint64_t)kTile) >> kSampleLog2);
+    for (uint32_t i = tid; i < (len >> kSampleLog2); i += kTileThreads)
+      samples[sbase + i] = sk[pad16((i << kSampleLog2) + kSample - 1)];
   }
 }
 
@@ -589,6 +596,240 @@ __global__ __launch_bounds__(kCorankThreads) void corank_kernel(
   }
 }
 
+// Same search for groups of at most 64 runs, one lane per run: the prefix
+// bounds live in registers, each level's candidates are loaded one per slot
+// by all lanes at once and sorted in registers by a bitonic network across the
+// wave (slot s = lane + 64 e), and the two prefix counts are read off with LDS
+// atomics.  E = largest number of slots per lane (3 * 64 candidates < 64 * 4).
+template <typename U, int E>
+__device__ __forceinline__ void cas(U &ka, uint32_t &ta, U &kb, uint32_t &tb, bool up) {
+  const bool gt = ka > kb || (ka == kb && ta > tb);
+  if (gt == up) {
+    const U k = ka;
+    ka = kb;
+    kb = k;
+    const uint32_t t = ta;
+    ta = tb;
+    tb = t;
+  }
+}
+
+// Merged samples of one pass: the group's level-kSampleLog2 samples in
+// (key, run, position) order as run ids, plus per-run prefix counts at every
+// kChunk-th merged sample.  They give V_5(Q) for any Q without a search.
+struct SampleIndex {
+  const uint32_t *runs;  // run id of every merged sample
+  const uint32_t *prefix; // [chunk][fan]: samples of each run before the chunk
+  RunGeom gs;             // geometry of the sample array (groups align with data)
+};
+
+template <typename U, int E, bool SAMPLED>
+__global__ __launch_bounds__(kCorankThreads) void corank_wave_kernel(
+    const U *__restrict__ src, RunGeom g, uint32_t *__restrict__ table,
+    U *__restrict__ pivots, uint64_t *__restrict__ counts, int kt, SampleIndex si) {
+  __shared__ uint32_t slot_run[64 * E];
+  __shared__ uint32_t cnt[2 * 64];
+
+  const uint32_t lane = threadIdx.x;
+  const uint64_t row = blockIdx.x;
+  const RowInfo ri = row_info(g, row, table);
+  const uint64_t glen = ri.grp.len, R = g.run_len, r = ri.rank;
+  const uint32_t nruns = glen ? (uint32_t)((glen + R - 1) / R) : 0;
+  const uint32_t len = lane < nruns ? run_length(glen, R, lane) : 0u;
+  const U *run = src + ri.grp.start + (uint64_t)lane * R;
+
+  uint32_t A = 0, B = 0;
+  if (r == 0 || r >= glen) {
+    A = r == 0 ? 0u : len;
+  } else {
+    const uint32_t maxlen = (uint32_t)(R < glen ? R : glen);
+    const uint32_t lastlen = run_length(glen, R, nruns - 1);
+    const int J = 32 - __clz(maxlen);
+    auto q_lo_at = [&](int j) -> uint64_t {
+      const int64_t num = (int64_t)r - (int64_t)((((uint64_t)1 << j) - 1) * (uint64_t)(nruns - 1));
+      return num > 0 ? ((uint64_t)num >> j) : 0;
+    };
+    int jtop = J;
+    if constexpr (SAMPLED) {
+      if (J > kSampleLog2) {
+        // Start at level kSampleLog2: V_5 at both bracket targets is read
+        // from the merged samples (prefix counts at the chunk + the run ids
+        // of the remaining < kChunk merged samples).
+        jtop = kSampleLog2;
+        const GroupInfo sg = group_of(si.gs, ri.grp.gi);
+        const uint64_t ns5 = sg.len;
+        // runs with at least one sample (a short last run may have none)
+        const uint64_t rs = si.gs.run_len;
+        const uint32_t nruns_s = ns5 ? (uint32_t)((ns5 + rs - 1) / rs) : 0u;
+        const uint64_t qs[2] = {q_lo_at(kSampleLog2),
+                                (r >> kSampleLog2) < ns5 ? (r >> kSampleLog2) : ns5};
+        const uint64_t prow0 = ri.grp.gi * (uint64_t)(si.gs.rows_per_group - 1) * (kPart / kChunk);
+        uint32_t v[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const uint64_t Q = qs[t];
+          cnt[lane] = 0;
+          __syncthreads();
+          uint32_t base_cnt = 0;
+          if (Q >= ns5) {
+            base_cnt = len >> kSampleLog2;
+          } else {
+            const uint64_t C = Q / kChunk;
+            const uint32_t rem = (uint32_t)(Q - C * kChunk);
+            if (lane < nruns_s) base_cnt = si.prefix[(prow0 + C) * g.fan + lane];
+            if (lane < rem) atomicAdd(&cnt[si.runs[sg.start + C * kChunk + lane]], 1u);
+          }
+          __syncthreads();
+          v[t] = base_cnt + (Q >= ns5 ? 0u : cnt[lane]);
+          __syncthreads();
+        }
+        A = lane < nruns ? v[0] : 0u;
+        B = lane < nruns ? v[1] : 0u;
+      }
+    }
+    for (int j = jtop - 1; j >= 0; --j) {
+      const uint64_t h = (uint64_t)1 << j;
+      const uint64_t ns_total = (uint64_t)(nruns - 1) * (R >> j) + (lastlen >> j);
+      const uint64_t q_lo = q_lo_at(j);
+      const uint64_t q_hi = (r >> j) < ns_total ? (r >> j) : ns_total;
+      const uint64_t base = 2 * q_lo_at(j + 1);
+
+      const uint32_t ns = len >> j;
+      const uint32_t lo_i = 2 * A + 1;
+      const uint32_t hi_i = 2 * B + 1 < ns ? 2 * B + 1 : ns;
+      const uint32_t c = hi_i >= lo_i ? hi_i - lo_i + 1 : 0u;
+      uint32_t incl = c;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, 64);
+        if ((int)lane >= d) incl += y;
+      }
+      const uint32_t off = incl - c;
+      uint32_t C = __shfl(incl, 63, 64);
+      if (C > 64u * E) {
+        if (lane == 0) report(kErrCandidates);
+        C = 64u * E;
+      }
+      for (uint32_t x = 0; x < c; ++x)
+        if (off + x < 64u * E) slot_run[off + x] = lane;
+      cnt[lane] = 0;
+      cnt[lane + 64] = 0;
+      __syncthreads();
+
+      uint32_t Cp = 64;
+      while (Cp < C) Cp <<= 1;
+      U key[E];
+      uint32_t tie[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const uint32_t s = lane + 64 * e;
+        // all lanes take part in the shuffles (no lane may be masked off)
+        const uint32_t rb = s < C ? slot_run[s] : 0u;
+        const uint32_t rb_off = __shfl(off, (int)rb, 64);
+        const uint32_t rb_a = __shfl(A, (int)rb, 64);
+        key[e] = key_max<U>();
+        tie[e] = 0xffffffffu;
+        if (s < C) {
+          const uint32_t x = s - rb_off;
+          key[e] = src[ri.grp.start + (uint64_t)rb * R + (uint64_t)(2 * rb_a + 1 + x) * h - 1];
+          tie[e] = (rb << 20) | x;
+        }
+      }
+
+      // bitonic sort of Cp slots, ascending by (key, tie)
+      for (uint32_t k = 2; k <= Cp; k <<= 1) {
+        for (uint32_t d = k >> 1; d > 0; d >>= 1) {
+          if (d >= 64) {
+            const uint32_t de = d >> 6;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+              if (E > 1 && ((uint32_t)e & de) == 0 && (e | (int)de) < E && 64u * (e | de) < Cp) {
+                const bool up = ((lane + 64u * e) & k) == 0;
+                if (de == 1) cas<U, E>(key[e], tie[e], key[e | 1], tie[e | 1], up);
+                else if (de == 2) cas<U, E>(key[e], tie[e], key[(e | 2) & (E - 1)], tie[(e | 2) & (E - 1)], up);
+              }
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+              if (64u * e < Cp) {
+                const U ok = __shfl_xor(key[e], (int)d, 64);
+                const uint32_t ot = __shfl_xor(tie[e], (int)d, 64);
+                const uint32_t idx = lane + 64u * e;
+                const bool lower = (lane & d) == 0;
+                const bool up = (idx & k) == 0;
+                const bool mine_gt = key[e] > ok || (key[e] == ok && tie[e] > ot);
+                // the lower slot keeps the smaller when ascending
+                const bool take_other = (lower == up) ? mine_gt : !mine_gt;
+                key[e] = take_other ? ok : key[e];
+                tie[e] = take_other ? ot : tie[e];
+              }
+            }
+          }
+        }
+      }
+
+      uint64_t rho_lo = q_lo - base, rho_hi = q_hi - base;
+      if (q_lo < base || q_hi < base || rho_hi > C || rho_lo > rho_hi) {
+        if (lane == 0) report(kErrBracket);
+        rho_lo = rho_lo > C ? C : rho_lo;
+        rho_hi = rho_hi > C ? C : rho_hi;
+        rho_lo = rho_lo > rho_hi ? rho_hi : rho_lo;
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const uint32_t s = lane + 64 * e;
+        if (s < rho_hi) {
+          const uint32_t rb = tie[e] >> 20;
+          atomicAdd(&cnt[64 + rb], 1u);
+          if (s < rho_lo) atomicAdd(&cnt[rb], 1u);
+        }
+      }
+      __syncthreads();
+      const uint32_t a = A;
+      A = 2 * a + cnt[lane];
+      B = 2 * a + cnt[64 + lane];
+      __syncthreads();
+    }
+  }
+  if (lane < g.fan) ri.out[lane] = lane < nruns ? A : 0u;
+
+  if (pivots != nullptr && g.paper) {
+    const uint64_t p = row / g.sub_per_part;
+    if (row % g.sub_per_part != 0 || p == 0 || p >= g.n_parts) return;
+    if (r == 0) {
+      if (lane == 0) {
+        pivots[p - 1] = 0;
+        counts[p - 1] = 0;
+      }
+      return;
+    }
+    U best = 0;
+    if (lane < nruns && A > 0) best = run[A - 1];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      const U o = __shfl_xor(best, d, 64);
+      best = o > best ? o : best;
+    }
+    uint64_t lt = 0;
+    if (lane < nruns) {
+      uint32_t lo = 0, hi = len;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (run[mid] < best) lo = mid + 1;
+        else hi = mid;
+      }
+      lt = lo;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) lt += __shfl_xor(lt, d, 64);
+    if (lane == 0) {
+      pivots[p - 1] = unmap_runtime<U>(best, kt);
+      counts[p - 1] = r - lt;
+    }
+  }
+}
+
 // --------------------------------------------------------------- K5 -------
 struct PartInfo {
   bool valid;
@@ -642,18 +883,26 @@ __device__ __forceinline__ uint32_t find_segment(const uint32_t *soff, uint32_t 
   return lo;
 }
 
-template <int KT, bool KV, uint32_t MAXF>
+// VMODE: 0 keys only, 1 keys + uint32 payload, 2 samples merge: the payload
+// is the index of the run each key came from, and per-run prefix counts at
+// every kChunk-th output are written to `prefix` (for the splitter search of
+// the data pass).  samples != nullptr: write every kSample-th output key of
+// each output run (run = this pass's group) for the next pass.
+template <int KT, int VMODE, uint32_t MAXF>
 __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
     const typename Key<KT>::U *__restrict__ src, const uint32_t *__restrict__ vsrc,
     typename Key<KT>::U *__restrict__ dst, uint32_t *__restrict__ vdst, RunGeom g,
-    const uint32_t *__restrict__ table, const uint64_t *__restrict__ part_off, int final_pass) {
+    const uint32_t *__restrict__ table, const uint64_t *__restrict__ part_off, int final_pass,
+    typename Key<KT>::U *__restrict__ samples, uint32_t *__restrict__ prefix) {
   using U = typename Key<KT>::U;
+  constexpr bool KV = VMODE != 0;
   constexpr uint32_t P = kPart + kPart / 16;
   __shared__ U sk[P];
   __shared__ uint32_t sv[KV ? P : 1];
   __shared__ uint32_t soff[MAXF + 1];
   __shared__ uint64_t ssrc[MAXF];
   __shared__ uint32_t wsum[kMergeThreads / 64 + 1];
+  __shared__ uint32_t hist[VMODE == 2 ? (kPart / kChunk) * kMaxSampledFan : 1];
 
   const uint32_t tid = threadIdx.x;
   const PartInfo pi = part_info(g, blockIdx.x, table, part_off);
@@ -677,17 +926,37 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
     return;
   }
 
-  // gather the partition's segments (coalesced within each segment)
+  // gather the partition's segments (coalesced within each segment): first
+  // every source address, then all loads back to back, then the LDS stores
   {
+    uint64_t addr[kMergeItems];
+    uint32_t runid[VMODE == 2 ? kMergeItems : 1];
     uint32_t b = tid < M ? find_segment(soff, F, tid) : 0;
 #pragma unroll
     for (int i = 0; i < kMergeItems; ++i) {
       const uint32_t idx = i * kMergeThreads + tid;
+      addr[i] = 0;
       if (idx < M) {
         while (soff[b + 1] <= idx) ++b;
-        const uint64_t s = ssrc[b] + (idx - soff[b]);
-        sk[pad16(idx)] = src[s];
-        if constexpr (KV) sv[pad16(idx)] = vsrc[s];
+        addr[i] = ssrc[b] + (idx - soff[b]);
+      }
+      if constexpr (VMODE == 2) runid[i] = b;
+    }
+    U kreg[kMergeItems];
+    uint32_t vreg[KV ? kMergeItems : 1];
+#pragma unroll
+    for (int i = 0; i < kMergeItems; ++i) {
+      const uint32_t idx = i * kMergeThreads + tid;
+      kreg[i] = idx < M ? src[addr[i]] : U(0);
+      if constexpr (VMODE == 1) vreg[i] = idx < M ? vsrc[addr[i]] : 0u;
+      if constexpr (VMODE == 2) vreg[i] = runid[i];
+    }
+#pragma unroll
+    for (int i = 0; i < kMergeItems; ++i) {
+      const uint32_t idx = i * kMergeThreads + tid;
+      if (idx < M) {
+        sk[pad16(idx)] = kreg[i];
+        if constexpr (KV) sv[pad16(idx)] = vreg[i];
       }
     }
   }
@@ -776,6 +1045,32 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
       if constexpr (KV) vdst[pi.out_off + idx] = sv[pad16(idx)];
     }
   }
+  if (samples != nullptr && !g.paper) {
+    // this partition starts at group position rlo, a multiple of kSample
+    const uint64_t gi = blockIdx.x / (g.rows_per_group - 1);
+    const uint64_t seg = gi / g.groups_per_seg, gg = gi % g.groups_per_seg;
+    const uint64_t rlo = pi.out_off - pi.group_start;
+    const uint64_t sbase = seg * (g.seg_len >> kSampleLog2) + ((gg * g.group_len + rlo) >> kSampleLog2);
+    for (uint32_t i = tid; i < (M >> kSampleLog2); i += kMergeThreads)
+      samples[sbase + i] = sk[pad16((i << kSampleLog2) + kSample - 1)];
+  }
+  if constexpr (VMODE == 2) {
+    // per-run prefix counts at every kChunk-th output of this partition
+    const uint32_t nch = (M + kChunk - 1) / kChunk;
+    for (uint32_t i = tid; i < nch * F; i += kMergeThreads) hist[i] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < M; i += kMergeThreads)
+      atomicAdd(&hist[(i / kChunk) * F + sv[pad16(i)]], 1u);
+    __syncthreads();
+    const uint64_t prow0 = (uint64_t)blockIdx.x * (kPart / kChunk);
+    for (uint32_t b = tid; b < F; b += kMergeThreads) {
+      uint32_t run = pi.lo_row[b];
+      for (uint32_t c = 0; c < nch; ++c) {
+        prefix[(prow0 + c) * g.fan + b] = run;
+        run += hist[c * F + b];
+      }
+    }
+  }
 }
 
 // --------------------------------------------------------------- K4 -------
@@ -862,9 +1157,22 @@ hipError_t dispatch_kt(int kt, F &&f) {
 }  // namespace
 
 // ------------------------------------------------------------ launchers ---
+RunGeom sample_geom(const RunGeom &g) {
+  RunGeom s = g;
+  const uint64_t nseg = (g.n + g.seg_len - 1) / g.seg_len;
+  const uint64_t last = g.n - (nseg - 1) * g.seg_len;
+  s.seg_len = g.seg_len >> kSampleLog2;
+  s.n = (nseg - 1) * s.seg_len + (last >> kSampleLog2);
+  s.run_len = g.run_len >> kSampleLog2;
+  s.group_len = g.group_len >> kSampleLog2;
+  s.part_len = kPart;
+  s.rows_per_group = (uint32_t)((s.group_len + kPart - 1) / kPart) + 1;
+  return s;
+}
+
 hipError_t launch_tile_sort(int kt, bool kv, const void *in, const uint32_t *vin, void *out,
                             uint32_t *vout, uint64_t n, uint64_t seg_len, int final_pass,
-                            hipStream_t s) {
+                            void *samples, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const uint64_t tps = (seg_len + kTile - 1) / kTile;
   const uint64_t nseg = (n + seg_len - 1) / seg_len;
@@ -874,10 +1182,10 @@ hipError_t launch_tile_sort(int kt, bool kv, const void *in, const uint32_t *vin
     using U = typename Key<KT>::U;
     if (kv)
       hipLaunchKernelGGL((tile_sort_kernel<KT, true>), dim3((uint32_t)grid), dim3(kTileThreads), 0, s,
-                         (const U *)in, vin, (U *)out, vout, n, seg_len, tps, final_pass);
+                         (const U *)in, vin, (U *)out, vout, n, seg_len, tps, final_pass, (U *)samples);
     else
       hipLaunchKernelGGL((tile_sort_kernel<KT, false>), dim3((uint32_t)grid), dim3(kTileThreads), 0, s,
-                         (const U *)in, vin, (U *)out, vout, n, seg_len, tps, final_pass);
+                         (const U *)in, vin, (U *)out, vout, n, seg_len, tps, final_pass, (U *)samples);
     return hipGetLastError();
   });
 }
@@ -894,9 +1202,18 @@ hipError_t launch_corank(int kt, const void *src, const RunGeom &g, uint32_t *ta
     return hipGetLastError();
   };
   const bool wide = key_bytes(kt) == 8;
-  if (g.fan <= 64)
-    return wide ? go(uint64_t{}, std::integral_constant<uint32_t, 64>{})
-                : go(uint32_t{}, std::integral_constant<uint32_t, 64>{});
+  if (g.fan <= 64) {
+    const SampleIndex none{nullptr, nullptr, g};
+    if (wide)
+      hipLaunchKernelGGL((corank_wave_kernel<uint64_t, 4, false>), dim3((uint32_t)rows),
+                         dim3(kCorankThreads), 0, s, (const uint64_t *)src, g, table,
+                         (uint64_t *)pivots, counts, kt, none);
+    else
+      hipLaunchKernelGGL((corank_wave_kernel<uint32_t, 4, false>), dim3((uint32_t)rows),
+                         dim3(kCorankThreads), 0, s, (const uint32_t *)src, g, table,
+                         (uint32_t *)pivots, counts, kt, none);
+    return hipGetLastError();
+  }
   if (g.fan <= 512)
     return wide ? go(uint64_t{}, std::integral_constant<uint32_t, 512>{})
                 : go(uint32_t{}, std::integral_constant<uint32_t, 512>{});
@@ -906,27 +1223,61 @@ hipError_t launch_corank(int kt, const void *src, const RunGeom &g, uint32_t *ta
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_merge(int kt, bool kv, const void *src, const uint32_t *vsrc, void *dst,
+hipError_t launch_corank_sampled(int kt, const void *src, const RunGeom &g, uint32_t *table,
+                                 const uint32_t *sample_runs, const uint32_t *sample_prefix,
+                                 hipStream_t s) {
+  const uint64_t rows = g.total_rows();
+  if (rows == 0) return hipSuccess;
+  if (g.fan > kMaxSampledFan || g.paper) return hipErrorInvalidValue;
+  const SampleIndex si{sample_runs, sample_prefix, sample_geom(g)};
+  if (key_bytes(kt) == 8)
+    hipLaunchKernelGGL((corank_wave_kernel<uint64_t, 4, true>), dim3((uint32_t)rows),
+                       dim3(kCorankThreads), 0, s, (const uint64_t *)src, g, table,
+                       (uint64_t *)nullptr, (uint64_t *)nullptr, kt, si);
+  else
+    hipLaunchKernelGGL((corank_wave_kernel<uint32_t, 4, true>), dim3((uint32_t)rows),
+                       dim3(kCorankThreads), 0, s, (const uint32_t *)src, g, table,
+                       (uint32_t *)nullptr, (uint64_t *)nullptr, kt, si);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge(int kt, int vmode, const void *src, const uint32_t *vsrc, void *dst,
                         uint32_t *vdst, const RunGeom &g, const uint32_t *table,
-                        const uint64_t *part_offsets, int final_pass, hipStream_t s) {
+                        const uint64_t *part_offsets, int final_pass, void *samples,
+                        uint32_t *prefix, hipStream_t s) {
   const uint64_t parts = g.total_parts();
   if (parts == 0) return hipSuccess;
+  if (vmode == 2) {
+    // sample arrays hold mapped keys: merge them as plain unsigned integers
+    if (g.fan > kMaxSampledFan || final_pass || samples) return hipErrorInvalidValue;
+    if (key_bytes(kt) == 8)
+      hipLaunchKernelGGL((merge_kernel<2, 2, 64>), dim3((uint32_t)parts), dim3(kMergeThreads), 0, s,
+                         (const uint64_t *)src, vsrc, (uint64_t *)dst, vdst, g, table, part_offsets,
+                         0, (uint64_t *)nullptr, prefix);
+    else
+      hipLaunchKernelGGL((merge_kernel<0, 2, 64>), dim3((uint32_t)parts), dim3(kMergeThreads), 0, s,
+                         (const uint32_t *)src, vsrc, (uint32_t *)dst, vdst, g, table, part_offsets,
+                         0, (uint32_t *)nullptr, prefix);
+    return hipGetLastError();
+  }
   return dispatch_kt(kt, [&](auto ktc) {
     constexpr int KT = decltype(ktc)::value;
     using U = typename Key<KT>::U;
-    auto go = [&](auto kvc, auto maxf) -> hipError_t {
-      constexpr bool KV = decltype(kvc)::value;
+    auto go = [&](auto vm, auto maxf) -> hipError_t {
+      constexpr int VM = decltype(vm)::value;
       constexpr uint32_t MAXF = decltype(maxf)::value;
-      hipLaunchKernelGGL((merge_kernel<KT, KV, MAXF>), dim3((uint32_t)parts), dim3(kMergeThreads), 0, s,
-                         (const U *)src, vsrc, (U *)dst, vdst, g, table, part_offsets, final_pass);
+      hipLaunchKernelGGL((merge_kernel<KT, VM, MAXF>), dim3((uint32_t)parts), dim3(kMergeThreads), 0, s,
+                         (const U *)src, vsrc, (U *)dst, vdst, g, table, part_offsets, final_pass,
+                         (U *)samples, (uint32_t *)nullptr);
       return hipGetLastError();
     };
+    const bool kv = vmode == 1;
     if (g.fan <= 64)
-      return kv ? go(std::true_type{}, std::integral_constant<uint32_t, 64>{})
-                : go(std::false_type{}, std::integral_constant<uint32_t, 64>{});
+      return kv ? go(std::integral_constant<int, 1>{}, std::integral_constant<uint32_t, 64>{})
+                : go(std::integral_constant<int, 0>{}, std::integral_constant<uint32_t, 64>{});
     if (g.fan <= kMaxRuns)
-      return kv ? go(std::true_type{}, std::integral_constant<uint32_t, kMaxRuns>{})
-                : go(std::false_type{}, std::integral_constant<uint32_t, kMaxRuns>{});
+      return kv ? go(std::integral_constant<int, 1>{}, std::integral_constant<uint32_t, kMaxRuns>{})
+                : go(std::integral_constant<int, 0>{}, std::integral_constant<uint32_t, kMaxRuns>{});
     return hipErrorInvalidValue;
   });
 }

@@ -17,6 +17,10 @@ constexpr int kTile = kTileThreads * kTileItems;  // 8192 keys
 constexpr int kMergeThreads = 512;
 constexpr int kMergeItems = 16;
 constexpr int kPart = kMergeThreads * kMergeItems;  // 8192 keys
+// Outputs per thread and round of the LDS merge rounds: with at most 32 pairs
+// per round, ceil-rounded chunks of 17 keys still fit in kMergeThreads
+// ((8192 + 32 * 16) / 17 <= 512).
+constexpr int kRoundItems = 17;
 
 // Step 2 splitter search: one 64-lane workgroup per splitter.
 constexpr int kCorankThreads = 64;

@@ -170,7 +170,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_sort_kernel(
     typename Key<KT>::U *__restrict__ out, uint32_t *__restrict__ vout, uint64_t n,
     uint64_t seg_len, uint64_t tiles_per_seg, int final_pass, typename Key<KT>::U *__restrict__ samples) {
   using U = typename Key<KT>::U;
-  constexpr uint32_t P = kTile + kTile / 16;
+  constexpr uint32_t P = kTile + kTile / 16 + 1;  // +1: a merge step may read one past the end
   __shared__ U sk[P];
   __shared__ uint32_t sv[KV ? P : 1];
 
@@ -241,8 +241,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_sort_kernel(
       const bool takeA = ai < L && (bi >= L || ka <= kb);
       rk[i] = takeA ? ka : kb;
       if constexpr (KV) rv[i] = takeA ? va : vb;
-      uint32_t nxt = takeA ? a0 + ai + 1 : b0 + bi + 1;
-      nxt = nxt < (uint32_t)kTile ? nxt : (uint32_t)kTile - 1;
+      const uint32_t nxt = takeA ? a0 + ai + 1 : b0 + bi + 1;
       const U nk = sk[pad16(nxt)];
       ka = takeA ? nk : ka;
       kb = takeA ? kb : nk;
@@ -872,6 +871,50 @@ __device__ __forceinline__ PartInfo part_info(const RunGeom &g, uint64_t pidx,
   return pi;
 }
 
+// One chunk of a stable pairwise merge in LDS: the outputs [start, start+count)
+// of merging A = [A0, A1) and B = [A1, B1) (ties to A), into registers.  The
+// merge-path search finds how many of the first start-A0 outputs come from A;
+// then one output per step.  Reads one slot past B1 at most (LDS has slack).
+template <typename U, bool KV, int ITEMS>
+__device__ __forceinline__ void merge_chunk(const U *sk, const uint32_t *sv, uint32_t A0,
+                                            uint32_t A1, uint32_t B1, uint32_t start,
+                                            uint32_t count, U (&rk)[ITEMS],
+                                            uint32_t (&rv)[KV ? ITEMS : 1]) {
+  const uint32_t la = A1 - A0, lb = B1 - A1, d = start - A0;
+  uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (sk[pad16(A0 + mid)] <= sk[pad16(A1 + d - 1 - mid)]) lo = mid + 1;
+    else hi = mid;
+  }
+  uint32_t pa = A0 + lo, pb = A1 + (d - lo);
+  U ka = sk[pad16(pa)], kb = sk[pad16(pb)];
+  uint32_t va = 0, vb = 0;
+  if constexpr (KV) {
+    va = sv[pad16(pa)];
+    vb = sv[pad16(pb)];
+  }
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    if ((uint32_t)i < count) {
+      const bool takeA = pa < A1 && (pb >= B1 || ka <= kb);
+      rk[i] = takeA ? ka : kb;
+      if constexpr (KV) rv[i] = takeA ? va : vb;
+      const uint32_t nxt = (takeA ? pa : pb) + 1;
+      const U nk = sk[pad16(nxt)];
+      ka = takeA ? nk : ka;
+      kb = takeA ? kb : nk;
+      if constexpr (KV) {
+        const uint32_t nv = sv[pad16(nxt)];
+        va = takeA ? nv : va;
+        vb = takeA ? vb : nv;
+      }
+      pa += takeA ? 1u : 0u;
+      pb += takeA ? 0u : 1u;
+    }
+  }
+}
+
 // Largest b in [0, F) with soff[b] <= pos (requires pos < soff[F]).
 __device__ __forceinline__ uint32_t find_segment(const uint32_t *soff, uint32_t F, uint32_t pos) {
   uint32_t lo = 0, hi = F;
@@ -896,10 +939,11 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
     typename Key<KT>::U *__restrict__ samples, uint32_t *__restrict__ prefix) {
   using U = typename Key<KT>::U;
   constexpr bool KV = VMODE != 0;
-  constexpr uint32_t P = kPart + kPart / 16;
+  constexpr uint32_t P = kPart + kPart / 16 + 1;  // +1: a merge step may read one past the end
   __shared__ U sk[P];
   __shared__ uint32_t sv[KV ? P : 1];
   __shared__ uint32_t soff[MAXF + 1];
+  __shared__ uint32_t cpre[MAXF <= 64 ? 64 / 2 + 2 : 1];
   __shared__ uint64_t ssrc[MAXF];
   __shared__ uint32_t wsum[kMergeThreads / 64 + 1];
   __shared__ uint32_t hist[VMODE == 2 ? (kPart / kChunk) * kMaxSampledFan : 1];
@@ -964,6 +1008,51 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
 
   // rounds of pairwise stable merges: at width w, runs of w consecutive
   // segments are merged in pairs (the lower run wins ties)
+  if constexpr (MAXF <= 64) {
+    // Each pair's output is cut into chunks of kRoundItems that never cross
+    // into the next pair; a chunk prefix over pairs maps threads to chunks.
+    // With at most 32 pairs, M <= kPart keys fit in kMergeThreads chunks.
+    constexpr int CI = kRoundItems;
+    for (uint32_t w = 1; w < F; w <<= 1) {
+      const uint32_t npairs = (F + 2 * w - 1) / (2 * w);
+      for (uint32_t q = tid; q < npairs; q += kMergeThreads) {
+        const uint32_t a0 = soff[2 * w * q];
+        const uint32_t b1 = soff[2 * w * q + 2 * w < F ? 2 * w * q + 2 * w : F];
+        cpre[q] = (b1 - a0 + CI - 1) / CI;
+      }
+      __syncthreads();
+      block_exclusive_scan(cpre, npairs, wsum);
+      const uint32_t nchunks = cpre[npairs];
+      if (nchunks > kMergeThreads && tid == 0) report(kErrPartSize);  // cannot happen for M <= kPart
+      U rk[CI];
+      uint32_t rv[KV ? CI : 1];
+      uint32_t start = 0, count = 0;
+      if (tid < nchunks) {
+        uint32_t lo = 0, hi = npairs;  // pair q with cpre[q] <= tid < cpre[q+1]
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (cpre[mid] <= tid) lo = mid;
+          else hi = mid;
+        }
+        const uint32_t s0 = 2 * w * lo;
+        const uint32_t A0 = soff[s0];
+        const uint32_t A1 = soff[s0 + w < F ? s0 + w : F];
+        const uint32_t B1 = soff[s0 + 2 * w < F ? s0 + 2 * w : F];
+        start = A0 + (tid - cpre[lo]) * CI;
+        count = B1 - start < (uint32_t)CI ? B1 - start : (uint32_t)CI;
+        merge_chunk<U, KV, CI>(sk, sv, A0, A1, B1, start, count, rk, rv);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < CI; ++i) {
+        if ((uint32_t)i < count) {
+          sk[pad16(start + i)] = rk[i];
+          if constexpr (KV) sv[pad16(start + i)] = rv[i];
+        }
+      }
+      __syncthreads();
+    }
+  } else {
   const uint32_t p0 = tid * kMergeItems;
   for (uint32_t w = 1; w < F; w <<= 1) {
     U rk[kMergeItems];
@@ -1034,6 +1123,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
       }
     }
     __syncthreads();
+  }
   }
 
 #pragma unroll

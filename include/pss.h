@@ -158,6 +158,43 @@ pss_status pss_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, uint6
                          size_t ws_bytes, void *stream);
 
 /*
+ * Batched segmented sort: sort each segment [seg_offsets[i], seg_offsets[i+1])
+ * of one array independently (ascending; key-value sorts stable within the
+ * segment), all segments in one fixed sequence of launches with no host round
+ * trip, so the sequence can be captured once into a hipGraph and replayed.
+ * The segments' shapes are read on the device: a planning kernel classifies
+ * every segment (one small tile, or tiles of 8192 keys plus merge passes of
+ * fan-in 32 with exact splitting, the paper's steps 2-4 applied per segment),
+ * and every later kernel finds its segment through the plan's prefix tables.
+ *
+ *   seg_offsets: DEVICE array of n_segs + 1 uint64, seg_offsets[0] = 0,
+ *     non-decreasing, seg_offsets[n_segs] = n.  Invalid offsets leave the
+ *     output unspecified and set bit 16 of the device error word
+ *     (pss_device_check).
+ *   tuning (host, may be NULL = defaults): which segments go to the smaller
+ *     tile sorts, and a bound on the longest segment that bounds the number
+ *     of merge passes launched.  Chosen by the project's autotuner per
+ *     workload; any valid tuning gives the same output.
+ *   Other arguments as pss_sort (n keys in total, out of place, caller-owned
+ *   workspace of pss_segmented_workspace_bytes bytes).
+ */
+typedef struct {
+  uint32_t small_max_2k; /* segments with <= this many keys: 2048-key tiles, 128 threads (<= 2048) */
+  uint32_t small_max_4k; /* segments with <= this many keys: 4096-key tiles, 256 threads (<= 4096) */
+  uint64_t max_seg_len;  /* upper bound on any segment's length; 0 = n */
+} pss_tuning;
+
+#define PSS_MAX_SEGMENTS 16777216u
+
+pss_status pss_segmented_workspace_bytes(const pss_ctx *ctx, pss_key_t key, pss_val_t val,
+                                         uint64_t n, uint32_t n_segs, const pss_tuning *tuning,
+                                         size_t *bytes);
+pss_status pss_segmented_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys_in,
+                              void *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
+                              uint64_t n, const uint64_t *seg_offsets, uint32_t n_segs,
+                              const pss_tuning *tuning, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Per-launch timing for measurement.  While enabled, every kernel launch that
  * a call on ctx makes is bracketed by two HIP events recorded on that call's
  * stream (a few microseconds of overhead per launch).  pss_profile_read waits
@@ -177,6 +214,8 @@ pss_status pss_profile_read(pss_ctx *ctx, char *buf, size_t buf_len);
  * target outside its bracket, 4 = split position outside its run, 8 = merged
  * segments do not add up to their partition.  A kernel that sets a bit stops
  * before writing outside its own partition, and its output is then invalid.
+ * Bit 16: segment offsets of pss_segmented_sort invalid (or a segment needing
+ * more merge passes than tuning->max_seg_len allowed for).
  * Meant for tests and debugging; it synchronises the whole device.
  */
 pss_status pss_device_check(pss_ctx *ctx, uint32_t *code);

@@ -16,9 +16,9 @@ import threading
 import torch
 
 from . import _lib
-from ._lib import PssError, plan, validate, workspace_bytes  # noqa: F401
+from ._lib import PssError, Tuning, plan, validate, workspace_bytes  # noqa: F401
 
-__all__ = ["sort", "splitters", "device_check", "key_type_of", "plan", "workspace_bytes", "PssError",
+__all__ = ["sort", "segmented_sort", "splitters", "device_check", "Tuning", "key_type_of", "plan", "workspace_bytes", "PssError",
            "Workspace"]
 
 _DTYPE_KEY = {
@@ -118,6 +118,67 @@ def profile_read(device: int = 0) -> dict:
     """Per kernel family: launches, total ms and algorithmic bytes since the
     last read (waits for the recorded events)."""
     return _context(device).profile_read()
+
+
+def segmented_sort(keys: torch.Tensor, seg_offsets, vals: torch.Tensor | None = None,
+                   key_type: str | int | None = None, tuning: "Tuning | dict | None" = None,
+                   max_seg_len: int | None = None, out: torch.Tensor | None = None,
+                   vals_out: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    """Sort every segment [seg_offsets[i], seg_offsets[i+1]) of a 1-D device
+    tensor independently (stable with `vals`).  seg_offsets: a device int64
+    tensor of n_segs + 1 offsets, or a host sequence (copied to the device;
+    its longest segment then bounds the merge passes launched).  `tuning`
+    chooses the small-segment tile sorts (see autotune.py); None = defaults,
+    or the autotuner's cached choice when one exists.  Returns (keys, vals)."""
+    if not keys.is_cuda or keys.dim() != 1 or not keys.is_contiguous():
+        raise ValueError("keys must be a contiguous 1-D device tensor")
+    kt = key_type_of(keys, key_type)
+    dev = keys.device.index if keys.device.index is not None else torch.cuda.current_device()
+    n = keys.numel()
+    if isinstance(seg_offsets, torch.Tensor) and seg_offsets.is_cuda:
+        offs = seg_offsets.to(torch.int64).contiguous()
+    else:
+        import numpy as np
+
+        host = np.asarray(seg_offsets, dtype=np.int64)
+        if max_seg_len is None and host.size > 1:
+            max_seg_len = int(np.max(np.diff(host)))
+        offs = torch.from_numpy(host).to(keys.device)
+    n_segs = offs.numel() - 1
+    vt = _lib.VAL_NONE
+    if vals is not None:
+        if not vals.is_cuda or vals.numel() != n or vals.element_size() != 4:
+            raise ValueError("vals must be a device tensor of n 4-byte elements")
+        vt = _lib.VAL_U32
+    tu = _resolve_tuning(tuning, kt, vt, n, n_segs, max_seg_len)
+    if out is None:
+        out = torch.empty_like(keys)
+    if vals is not None and vals_out is None:
+        vals_out = torch.empty_like(vals)
+    need = _lib.segmented_workspace_bytes(kt, vt, n, n_segs, tu)
+    ws = workspace if workspace is not None else Workspace.get(dev, need)
+    _context(dev).segmented_sort(kt, vt, keys.data_ptr(), out.data_ptr(),
+                                 vals.data_ptr() if vals is not None else 0,
+                                 vals_out.data_ptr() if vals is not None else 0,
+                                 n, offs.data_ptr(), n_segs, tu, ws.data_ptr(), ws.numel(),
+                                 _stream_handle(dev))
+    return out, (vals_out if vals is not None else None)
+
+
+def _resolve_tuning(tuning, kt, vt, n, n_segs, max_seg_len):
+    if isinstance(tuning, _lib.Tuning):
+        tu = tuning
+    else:
+        d = tuning
+        if d is None:
+            from . import autotune
+
+            d = autotune.cached(kt, vt, n, n_segs)
+        tu = _lib.Tuning(int(d.get("small_max_2k", 2048)) if d else 2048,
+                         int(d.get("small_max_4k", 4096)) if d else 4096, 0)
+    if max_seg_len is not None and tu.max_seg_len == 0:
+        tu = _lib.Tuning(tu.small_max_2k, tu.small_max_4k, int(max_seg_len))
+    return tu
 
 
 def device_check(device: int = 0) -> int:

@@ -35,6 +35,9 @@ SIGNATURES = {
     "pss_plan_describe": (_int, [_int, _int, _u64, _u32, _u32, _c.c_char_p, _sz]),
     "pss_sort": (_int, [_vp, _int, _int, _vp, _vp, _vp, _vp, _u64, _u32, _u32, _vp, _sz, _vp]),
     "pss_device_check": (_int, [_vp, _c.POINTER(_u32)]),
+    "pss_segmented_workspace_bytes": (_int, [_vp, _int, _int, _u64, _u32, _vp, _c.POINTER(_sz)]),
+    "pss_segmented_sort": (_int, [_vp, _int, _int, _vp, _vp, _vp, _vp, _u64, _vp, _u32, _vp, _vp,
+                                  _sz, _vp]),
     "pss_profile_enable": (_int, [_vp, _int]),
     "pss_profile_read": (_int, [_vp, _c.c_char_p, _sz]),
     "pss_splitters": (_int, [_vp, _int, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
@@ -102,6 +105,27 @@ def plan(key: int, val: int, n: int, n_blocks: int = 0, n_parts: int = 0) -> dic
     return json.loads(buf.value.decode())
 
 
+class Tuning(ctypes.Structure):
+    """pss_tuning: which segments use the 2048- and 4096-key tile sorts, and a
+    bound on the longest segment (bounds the merge passes launched)."""
+
+    _fields_ = [("small_max_2k", ctypes.c_uint32), ("small_max_4k", ctypes.c_uint32),
+                ("max_seg_len", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {"small_max_2k": self.small_max_2k, "small_max_4k": self.small_max_4k,
+                "max_seg_len": self.max_seg_len}
+
+
+def segmented_workspace_bytes(key: int, val: int, n: int, n_segs: int,
+                              tuning: Tuning | None = None) -> int:
+    out = ctypes.c_size_t()
+    check(load().pss_segmented_workspace_bytes(None, key, val, n, n_segs,
+                                               ctypes.byref(tuning) if tuning else None,
+                                               ctypes.byref(out)))
+    return int(out.value)
+
+
 class Context:
     """One pss_ctx bound to a HIP device."""
 
@@ -136,6 +160,14 @@ class Context:
         buf = ctypes.create_string_buffer(1 << 16)
         check(self.lib.pss_profile_read(self.handle, buf, len(buf)), self.handle)
         return json.loads(buf.value.decode())
+
+    def segmented_sort(self, key: int, val: int, keys_in: int, keys_out: int, vals_in: int,
+                       vals_out: int, n: int, seg_offsets: int, n_segs: int,
+                       tuning: Tuning | None, ws: int, ws_bytes: int, stream: int) -> None:
+        check(self.lib.pss_segmented_sort(self.handle, key, val, keys_in or None, keys_out or None,
+                                          vals_in or None, vals_out or None, n, seg_offsets or None,
+                                          n_segs, ctypes.byref(tuning) if tuning else None,
+                                          ws or None, ws_bytes, stream or None), self.handle)
 
     def device_check(self) -> int:
         """Synchronise the device and return (and clear) the error word."""

@@ -512,6 +512,212 @@ pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys
   return PSS_OK;
 }
 
+// ------------------------------------------------- batched segmented sort
+namespace {
+
+struct SegPlan {
+  uint32_t max_passes = 0;
+  uint32_t small0 = 2048, small1 = 4096;
+  std::vector<pss::RunGeom> g, gs;  // per pass: key level and sample level
+  uint64_t ns = 0;                  // bound on samples
+  size_t off_keys = 0, off_vals = 0, off_plan = 0, off_samples = 0, off_skeys = 0;
+  size_t off_sruns = 0, off_table = 0, off_stable = 0, off_prefix = 0, total = 0;
+};
+
+uint32_t passes_for(uint64_t L) {
+  if (L <= (uint64_t)pss::kTile) return 0;
+  const uint64_t tiles = ceil_div(L, pss::kTile);
+  uint32_t bits = 0;
+  while (((uint64_t)1 << bits) < tiles) ++bits;
+  return (bits + pss::kMaxFanLog2 - 1) / pss::kMaxFanLog2;
+}
+
+pss_status make_seg_plan(const pss_ctx *ctx, pss_key_t key, pss_val_t val, uint64_t n,
+                         uint32_t n_segs, const pss_tuning *tu, SegPlan *sp) {
+  if ((int)key < 0 || (int)key > 5) return fail(ctx, PSS_ERR_INVALID, "unknown key type");
+  if ((int)val != PSS_VAL_NONE && (int)val != PSS_VAL_U32)
+    return fail(ctx, PSS_ERR_INVALID, "unknown value type");
+  if (n > PSS_MAX_KEYS) return fail(ctx, PSS_ERR_UNSUPPORTED, "n >= 2^31 is not supported");
+  if (n_segs > PSS_MAX_SEGMENTS) return fail(ctx, PSS_ERR_UNSUPPORTED, "too many segments");
+  uint64_t max_len = n;
+  if (tu) {
+    if (tu->small_max_2k > 2048 || tu->small_max_4k > 4096 || tu->small_max_2k > tu->small_max_4k)
+      return fail(ctx, PSS_ERR_INVALID, "tuning: need small_max_2k <= small_max_4k, <= 2048, <= 4096");
+    sp->small0 = tu->small_max_2k;
+    sp->small1 = tu->small_max_4k;
+    if (tu->max_seg_len) max_len = std::min<uint64_t>(tu->max_seg_len, n);
+  }
+  const int kb = pss::key_bytes((int)key);
+  const bool kv = val == PSS_VAL_U32;
+  sp->max_passes = passes_for(max_len);
+  sp->ns = n >> pss::kSampleLog2;
+  const uint64_t S = n_segs;
+  uint64_t max_rows = 0, max_srows = 0, max_sparts = 0;
+  for (uint32_t q = 1; q <= sp->max_passes; ++q) {
+    pss::RunGeom g{};
+    g.n = n;
+    g.run_len = (uint64_t)pss::kTile << (pss::kMaxFanLog2 * (q - 1));
+    g.fan = 1u << pss::kMaxFanLog2;
+    g.group_len = g.run_len << pss::kMaxFanLog2;
+    g.part_len = pss::kPart;
+    g.rows_per_group = (uint32_t)(g.group_len / pss::kPart) + 1;
+    const uint64_t groups = n / g.group_len + S + 1;
+    g.part_bound = n / pss::kPart + groups + 1;
+    g.row_bound = g.part_bound + groups + 1;
+    g.seg_len = g.group_len;
+    g.groups_per_seg = 1;
+    g.n_groups = groups;
+    pss::RunGeom gs = g;
+    gs.n = sp->ns;
+    gs.run_len = g.run_len >> pss::kSampleLog2;
+    gs.group_len = g.group_len >> pss::kSampleLog2;
+    gs.rows_per_group = (uint32_t)(gs.group_len / pss::kPart) + 1;
+    gs.part_bound = sp->ns / pss::kPart + groups + 1;
+    gs.row_bound = gs.part_bound + groups + 1;
+    max_rows = std::max(max_rows, g.row_bound);
+    max_srows = std::max(max_srows, gs.row_bound);
+    max_sparts = std::max(max_sparts, gs.part_bound);
+    sp->g.push_back(g);
+    sp->gs.push_back(gs);
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  sp->off_keys = take(n * (size_t)kb);
+  sp->off_vals = kv ? take(n * sizeof(uint32_t)) : 0;
+  // 3 tile prefixes, sample offsets, 4 prefixes per pass, then npass
+  sp->off_plan = take((4 + 4 * (size_t)pss::kMaxSegPasses) * (S + 1) * 8 + S * 4);
+  if (sp->max_passes) {
+    sp->off_samples = take(sp->ns * (size_t)kb);
+    sp->off_skeys = take(sp->ns * (size_t)kb);
+    sp->off_sruns = take(sp->ns * sizeof(uint32_t));
+    sp->off_table = take(max_rows * (1u << pss::kMaxFanLog2) * sizeof(uint32_t));
+    sp->off_stable = take(max_srows * (1u << pss::kMaxFanLog2) * sizeof(uint32_t));
+    sp->off_prefix =
+        take(max_sparts * (pss::kPart / pss::kChunk) * (1u << pss::kMaxFanLog2) * sizeof(uint32_t));
+  }
+  sp->total = off;
+  return PSS_OK;
+}
+
+pss::SegPlanPtrs seg_plan_ptrs(char *w, const SegPlan &sp, uint32_t n_segs) {
+  pss::SegPlanPtrs pp{};
+  uint64_t *a = (uint64_t *)(w + sp.off_plan);
+  const size_t stride = (size_t)n_segs + 1;
+  for (int c = 0; c < 3; ++c) pp.tiles[c] = a + c * stride;
+  pp.soff = a + 3 * stride;
+  for (uint32_t q = 0; q < pss::kMaxSegPasses; ++q) {
+    pp.rows[q] = a + (4 + 4 * q + 0) * stride;
+    pp.parts[q] = a + (4 + 4 * q + 1) * stride;
+    pp.srows[q] = a + (4 + 4 * q + 2) * stride;
+    pp.sparts[q] = a + (4 + 4 * q + 3) * stride;
+  }
+  pp.npass = (uint32_t *)(a + (4 + 4 * pss::kMaxSegPasses) * stride);
+  return pp;
+}
+
+}  // namespace
+
+pss_status pss_segmented_workspace_bytes(const pss_ctx *ctx, pss_key_t key, pss_val_t val,
+                                         uint64_t n, uint32_t n_segs, const pss_tuning *tuning,
+                                         size_t *bytes) {
+  if (!bytes) return fail(ctx, PSS_ERR_INVALID, "null output pointer");
+  SegPlan sp;
+  const pss_status st = make_seg_plan(ctx, key, val, n, n_segs, tuning, &sp);
+  if (st != PSS_OK) return st;
+  *bytes = sp.total;
+  return PSS_OK;
+}
+
+pss_status pss_segmented_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys_in,
+                              void *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
+                              uint64_t n, const uint64_t *seg_offsets, uint32_t n_segs,
+                              const pss_tuning *tuning, void *ws, size_t ws_bytes, void *stream) {
+  SegPlan sp;
+  pss_status st = make_seg_plan(ctx, key, val, n, n_segs, tuning, &sp);
+  if (st != PSS_OK) return st;
+  const size_t kbytes = (size_t)pss::key_bytes((int)key);
+  const bool kv = val == PSS_VAL_U32;
+  if (n > 0) {
+    if (!keys_in || !keys_out) return fail(ctx, PSS_ERR_INVALID, "null key pointer");
+    if (overlaps(keys_in, n * kbytes, keys_out, n * kbytes))
+      return fail(ctx, PSS_ERR_INVALID, "keys_in and keys_out overlap (the sort is out of place)");
+    if (kv) {
+      if (!vals_in || !vals_out) return fail(ctx, PSS_ERR_INVALID, "null value pointer");
+      if (overlaps(vals_in, n * 4, vals_out, n * 4) || overlaps(keys_out, n * kbytes, vals_out, n * 4))
+        return fail(ctx, PSS_ERR_INVALID, "value arrays overlap");
+    }
+    if (!seg_offsets || n_segs == 0) return fail(ctx, PSS_ERR_INVALID, "segment offsets missing");
+  }
+  if (ws_bytes < sp.total) {
+    char m[160];
+    snprintf(m, sizeof m, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, sp.total);
+    return fail(ctx, PSS_ERR_WORKSPACE, m);
+  }
+  if (!ctx) return fail(nullptr, PSS_ERR_INVALID, "null context");
+  if (n == 0) return PSS_OK;
+  if (!ws) return fail(ctx, PSS_ERR_WORKSPACE, "null workspace");
+  PSS_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int kt = (int)key;
+  char *w = (char *)ws;
+  const pss::SegPlanPtrs pp = seg_plan_ptrs(w, sp, n_segs);
+  void *kws = w + sp.off_keys;
+  uint32_t *vws = kv ? (uint32_t *)(w + sp.off_vals) : nullptr;
+  void *samples = sp.max_passes ? (void *)(w + sp.off_samples) : nullptr;
+  void *skeys = w + sp.off_skeys;
+  uint32_t *sruns = (uint32_t *)(w + sp.off_sruns);
+  uint32_t *table = (uint32_t *)(w + sp.off_table);
+  uint32_t *stable = (uint32_t *)(w + sp.off_stable);
+  uint32_t *prefix = (uint32_t *)(w + sp.off_prefix);
+  const uint64_t sweep = 2 * n * (kbytes + (kv ? 4 : 0));
+  {
+    LaunchTimer t(ctx, "segment_plan", (uint64_t)n_segs * 16, s);
+    PSS_TRY(pss::launch_seg_plan(seg_offsets, n_segs, n, pp, sp.small0, sp.small1, sp.max_passes, s),
+            "segment plan launch");
+  }
+  {
+    LaunchTimer t(ctx, "tile_sort", sweep, s);
+    PSS_TRY(pss::launch_seg_tile_sorts(kt, kv, keys_in, vals_in, keys_out, kws, vals_out, vws,
+                                       samples, seg_offsets, pp, n_segs, n, s),
+            "tile sort launch");
+  }
+  for (uint32_t q = 1; q <= sp.max_passes; ++q) {
+    pss::RunGeom g = sp.g[q - 1], gs = sp.gs[q - 1];
+    g.seg = pss::SegTables{seg_offsets, pp.soff, pp.npass, pp.rows[q - 1], pp.parts[q - 1],
+                           pp.sparts[q - 1], n_segs, q, 0};
+    gs.seg = pss::SegTables{seg_offsets, pp.soff, pp.npass, pp.srows[q - 1], pp.sparts[q - 1],
+                            pp.sparts[q - 1], n_segs, q, 1};
+    {
+      LaunchTimer t(ctx, "sample_split_search", gs.row_bound * gs.fan * 4, s);
+      PSS_TRY(pss::launch_corank(kt, samples, gs, stable, nullptr, nullptr, s),
+              "sample split search launch");
+    }
+    {
+      LaunchTimer t(ctx, "sample_merge", 2 * sp.ns * kbytes, s);
+      PSS_TRY(pss::launch_merge(kt, 2, samples, nullptr, skeys, sruns, gs, stable, nullptr, 0, nullptr,
+                                prefix, s),
+              "sample merge launch");
+    }
+    {
+      LaunchTimer t(ctx, "split_search", g.row_bound * g.fan * 4, s);
+      PSS_TRY(pss::launch_corank_sampled(kt, keys_out, g, table, sruns, prefix, s, kws, &gs),
+              "split search launch");
+    }
+    {
+      LaunchTimer t(ctx, "merge", sweep, s);
+      const pss::MergeAlt alt{kws, vws, kws, vws};
+      PSS_TRY(pss::launch_merge(kt, kv ? 1 : 0, keys_out, vals_out, keys_out, vals_out, g, table,
+                                nullptr, 0, samples, nullptr, s, &alt),
+              "merge launch");
+    }
+  }
+  return PSS_OK;
+}
+
 pss_status pss_device_check(pss_ctx *ctx, uint32_t *code) {
   if (!ctx || !code) return fail(ctx, PSS_ERR_INVALID, "null argument");
   PSS_TRY(hipSetDevice(ctx->device), "hipSetDevice");

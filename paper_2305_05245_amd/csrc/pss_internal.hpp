@@ -40,6 +40,20 @@ constexpr uint32_t kChunk = 64;
 // Largest fan-in for which the sampled search is used.
 constexpr uint32_t kMaxSampledFan = 32;
 
+// Per-segment tables of the batched segmented sort (all device arrays, filled
+// on the device by the planning kernel).  off == nullptr: not segmented.
+struct SegTables {
+  const uint64_t *off;    // key offsets of the segments [n_segs + 1]
+  const uint64_t *soff;   // offsets of each segment's samples [n_segs + 1]
+  const uint32_t *npass;  // merge passes each segment needs
+  const uint64_t *rows;   // prefix over segments of this pass's table rows
+  const uint64_t *parts;  // prefix over segments of this pass's partitions
+  const uint64_t *sparts; // prefix over segments of this pass's sample partitions
+  uint32_t n_segs;
+  uint32_t pass;   // 1-based merge pass described by this geometry
+  uint32_t level;  // 0 = keys, 1 = the sample array
+};
+
 // Geometry of one merge pass.  The array is cut into uniform segments of
 // seg_len keys (the last one short); inside a segment, sorted runs of run_len
 // keys are merged in groups of `fan` runs, each group's output cut into
@@ -60,10 +74,15 @@ struct RunGeom {
   int paper;
   uint32_t n_parts;       // paper mode: n_P
   uint32_t sub_per_part;  // paper mode: chunks per paper partition
+  SegTables seg;          // segmented mode (seg.off != nullptr)
+  uint64_t row_bound;     // segmented mode: grid upper bound for rows
+  uint64_t part_bound;    // segmented mode: grid upper bound for partitions
   uint64_t total_rows() const {
+    if (seg.off) return row_bound;
     return paper ? (uint64_t)n_parts * sub_per_part + 1 : n_groups * rows_per_group;
   }
   uint64_t total_parts() const {
+    if (seg.off) return part_bound;
     return paper ? (uint64_t)n_parts * sub_per_part : n_groups * (rows_per_group - 1);
   }
 };
@@ -73,6 +92,11 @@ constexpr uint32_t kErrCandidates = 1u;  // splitter search: candidate set overf
 constexpr uint32_t kErrBracket = 2u;     // splitter search: target outside bracket
 constexpr uint32_t kErrSplitRow = 4u;    // merge: split row not inside its run
 constexpr uint32_t kErrPartSize = 8u;    // merge: segments do not add up to the partition
+constexpr uint32_t kErrSegments = 16u;   // segmented sort: offsets invalid or too many passes
+
+// Largest number of merge passes of one segment (n < 2^31: 2^18 tiles, 5
+// doublings per pass).
+constexpr uint32_t kMaxSegPasses = 4;
 
 // Synchronous read (and optional clear) of the device error word.
 hipError_t read_device_error(uint32_t *code, bool clear);
@@ -83,23 +107,55 @@ inline int key_bytes(int kt) { return (kt == 0 || kt == 1 || kt == 4) ? 4 : 8; }
 // Geometry of the sample array of the runs described by g (same groups).
 RunGeom sample_geom(const RunGeom &g);
 
+// Tile sizes of the segmented mode's small-segment classes.
+constexpr int kSmallThreads0 = 128;  // 2048-key tiles
+constexpr int kSmallThreads1 = 256;  // 4096-key tiles
+
+// Device arrays of the segmented plan (see seg_plan_kernel).
+struct SegPlanPtrs {
+  uint64_t *tiles[3];
+  uint64_t *soff;
+  uint32_t *npass;
+  uint64_t *rows[kMaxSegPasses], *parts[kMaxSegPasses];
+  uint64_t *srows[kMaxSegPasses], *sparts[kMaxSegPasses];
+};
+
+// Second buffer set of a segmented merge (X_j not in the primary buffers).
+struct MergeAlt {
+  const void *src;
+  const uint32_t *vsrc;
+  void *dst;
+  uint32_t *vdst;
+};
+
 // samples: optional output, every kSample-th key of each sorted tile.
 hipError_t launch_tile_sort(int kt, bool kv, const void *in, const uint32_t *vin, void *out,
                             uint32_t *vout, uint64_t n, uint64_t seg_len, int final_pass,
                             void *samples, hipStream_t s);
+hipError_t launch_seg_plan(const uint64_t *seg_off, uint32_t n_segs, uint64_t n,
+                           const SegPlanPtrs &pp, uint32_t small0, uint32_t small1,
+                           uint32_t max_passes, hipStream_t s);
+hipError_t launch_seg_tile_sorts(int kt, bool kv, const void *in, const uint32_t *vin, void *out,
+                                 void *out_alt, uint32_t *vout, uint32_t *vout_alt, void *samples,
+                                 const uint64_t *seg_off, const SegPlanPtrs &pp, uint32_t n_segs,
+                                 uint64_t n, hipStream_t s);
+// src_alt: segmented mode's second input buffer (nullptr = same as src).
 hipError_t launch_corank(int kt, const void *src, const RunGeom &g, uint32_t *table,
-                         void *pivots, uint64_t *counts, hipStream_t s);
+                         void *pivots, uint64_t *counts, hipStream_t s,
+                         const void *src_alt = nullptr);
 // Splitter search that starts from the merged samples (see merge mode 2).
+// gs: geometry of the sample array (nullptr = derived from g, uniform mode).
 hipError_t launch_corank_sampled(int kt, const void *src, const RunGeom &g, uint32_t *table,
                                  const uint32_t *sample_runs, const uint32_t *sample_prefix,
-                                 hipStream_t s);
+                                 hipStream_t s, const void *src_alt = nullptr,
+                                 const RunGeom *gs = nullptr);
 // vmode 0: keys only; 1: keys + uint32 payload; 2: merge of a sample array,
 // payload = source run index, per-run prefix counts written to `prefix`.
 // samples: optional output, every kSample-th key of each output run.
 hipError_t launch_merge(int kt, int vmode, const void *src, const uint32_t *vsrc, void *dst,
                         uint32_t *vdst, const RunGeom &g, const uint32_t *table,
                         const uint64_t *part_offsets, int final_pass, void *samples,
-                        uint32_t *prefix, hipStream_t s);
+                        uint32_t *prefix, hipStream_t s, const MergeAlt *alt = nullptr);
 hipError_t launch_partition_offsets(const RunGeom &g, const uint32_t *table, uint64_t *sizes,
                                     uint64_t *offsets, hipStream_t s);
 hipError_t launch_split_table(const RunGeom &g, const uint32_t *table, uint64_t *split,

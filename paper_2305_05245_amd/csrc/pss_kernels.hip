@@ -158,35 +158,87 @@ __device__ __forceinline__ void register_sort(U (&k)[N], uint32_t (&v)[KV ? N : 
   }
 }
 
+// Largest s in [0, n_segs) with prefix[s] <= idx (prefix[0] = 0): the segment
+// whose range of a prefix-summed count contains idx.
+__device__ __forceinline__ uint32_t seg_find(const uint64_t *prefix, uint32_t n_segs, uint64_t idx) {
+  uint32_t lo = 0, hi = n_segs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (prefix[mid] <= idx) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // --------------------------------------------------------------- K1 -------
 // One workgroup sorts one tile of at most kTile keys of one segment.  Keys are
 // mapped on load (K0), each thread sorts 16 consecutive keys in registers, then
 // log2(kTile/16) rounds of stable merge-path merges run through LDS.  A short
 // tile is padded with the largest key; pads sit after every real key (for
 // key-value sorts the network and merges are stable, so pads stay last).
-template <int KT, bool KV>
-__global__ __launch_bounds__(kTileThreads) void tile_sort_kernel(
+// Where one tile-sort workgroup reads and writes.  Uniform mode: tiles of
+// kTile keys in uniform segments.  Segmented mode: `tiles` is the prefix over
+// segments of the tiles of this launch's tile size (0 for segments another
+// tile size handles); outputs go to the primary or alt buffer by the parity of
+// the segment's merge passes, and only segments with merge passes leave
+// samples.
+template <typename U> struct TileArgs {
+  uint64_t n, seg_len, tiles_per_seg;
+  int final_pass;
+  U *out, *out_alt;
+  uint32_t *vout, *vout_alt;
+  U *samples;
+  const uint64_t *seg_off, *tiles, *soff;
+  const uint32_t *npass;
+  uint32_t n_segs;
+};
+
+template <int KT, bool KV, int THREADS>
+__global__ __launch_bounds__(THREADS) void tile_sort_kernel(
     const typename Key<KT>::U *__restrict__ in, const uint32_t *__restrict__ vin,
-    typename Key<KT>::U *__restrict__ out, uint32_t *__restrict__ vout, uint64_t n,
-    uint64_t seg_len, uint64_t tiles_per_seg, int final_pass, typename Key<KT>::U *__restrict__ samples) {
+    TileArgs<typename Key<KT>::U> ta) {
   using U = typename Key<KT>::U;
-  constexpr uint32_t P = kTile + kTile / 16 + 1;  // +1: a merge step may read one past the end
+  constexpr uint32_t TILE = THREADS * kTileItems;
+  constexpr uint32_t P = TILE + TILE / 16 + 1;  // +1: a merge step may read one past the end
   __shared__ U sk[P];
   __shared__ uint32_t sv[KV ? P : 1];
 
   const uint32_t tid = threadIdx.x;
   const uint64_t t = blockIdx.x;
-  const uint64_t seg = t / tiles_per_seg, j = t % tiles_per_seg;
-  const uint64_t seg_start = seg * seg_len;
-  if (seg_start >= n) return;
-  const uint64_t seg_end = seg_start + seg_len < n ? seg_start + seg_len : n;
-  const uint64_t start = seg_start + j * (uint64_t)kTile;
-  if (start >= seg_end) return;
-  const uint32_t len = (uint32_t)(seg_end - start < (uint64_t)kTile ? seg_end - start : kTile);
+  uint64_t start, sbase = 0;
+  uint32_t len;
+  U *out = ta.out, *samples = ta.samples;
+  uint32_t *vout = ta.vout;
+  int final_pass = ta.final_pass;
+  if (ta.seg_off) {
+    if (t >= ta.tiles[ta.n_segs]) return;
+    const uint32_t sg = seg_find(ta.tiles, ta.n_segs, t);
+    const uint64_t j = t - ta.tiles[sg];
+    const uint64_t slen = ta.seg_off[sg + 1] - ta.seg_off[sg];
+    start = ta.seg_off[sg] + j * (uint64_t)TILE;
+    len = (uint32_t)(slen - j * TILE < (uint64_t)TILE ? slen - j * TILE : TILE);
+    const uint32_t np = ta.npass[sg];
+    if (np & 1u) {  // X_0 is the output only after an even number of passes
+      out = ta.out_alt;
+      vout = ta.vout_alt;
+    }
+    final_pass = np == 0;
+    if (np == 0) samples = nullptr;
+    sbase = ta.soff[sg] + ((j * (uint64_t)TILE) >> kSampleLog2);
+  } else {
+    const uint64_t seg = t / ta.tiles_per_seg, j = t % ta.tiles_per_seg;
+    const uint64_t seg_start = seg * ta.seg_len;
+    if (seg_start >= ta.n) return;
+    const uint64_t seg_end = seg_start + ta.seg_len < ta.n ? seg_start + ta.seg_len : ta.n;
+    start = seg_start + j * (uint64_t)TILE;
+    if (start >= seg_end) return;
+    len = (uint32_t)(seg_end - start < (uint64_t)TILE ? seg_end - start : TILE);
+    sbase = seg * (ta.seg_len >> kSampleLog2) + ((j * (uint64_t)TILE) >> kSampleLog2);
+  }
 
 #pragma unroll
   for (int i = 0; i < kTileItems; ++i) {
-    const uint32_t idx = i * kTileThreads + tid;
+    const uint32_t idx = i * THREADS + tid;
     U k = key_max<U>();
     uint32_t v = 0;
     if (idx < len) {
@@ -208,7 +260,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_sort_kernel(
   }
   register_sort<U, KV, kTileItems>(rk, rv);
 
-  for (uint32_t L = kTileItems; L < (uint32_t)kTile; L *= 2) {
+  for (uint32_t L = kTileItems; L < TILE; L *= 2) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kTileItems; ++i) {
@@ -264,7 +316,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_sort_kernel(
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kTileItems; ++i) {
-    const uint32_t idx = i * kTileThreads + tid;
+    const uint32_t idx = i * THREADS + tid;
     if (idx < len) {
       const U k = sk[pad16(idx)];
       out[start + idx] = final_pass ? Key<KT>::unmap(k) : k;
@@ -274,8 +326,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_sort_kernel(
   // regular samples of the sorted tile (every kSample-th key, tile positions
   // kSample*i + kSample-1) for the next level's splitter search
   if (samples != nullptr) {
-    const uint64_t sbase = seg * (seg_len >> kSampleLog2) + ((j * (uint64_t)kTile) >> kSampleLog2);
-    for (uint32_t i = tid; i < (len >> kSampleLog2); i += kTileThreads)
+    for (uint32_t i = tid; i < (len >> kSampleLog2); i += THREADS)
       samples[sbase + i] = sk[pad16((i << kSampleLog2) + kSample - 1)];
   }
 }
@@ -284,12 +335,36 @@ __global__ __launch_bounds__(kTileThreads) void tile_sort_kernel(
 struct GroupInfo {
   uint64_t start;  // first key of the group
   uint64_t len;    // keys in the group (0 = no such group)
-  uint64_t gi;     // group index (table block index)
+  uint64_t gi;     // group index (table block index; uniform mode)
+  uint32_t seg;    // segment (segmented mode)
+  uint64_t gg;     // group within the segment (segmented mode)
 };
+
+__device__ __forceinline__ GroupInfo seg_group(const RunGeom &g, uint32_t s, uint64_t gg) {
+  const uint64_t *base = g.seg.level ? g.seg.soff : g.seg.off;
+  const uint64_t sstart = base[s], slen = base[s + 1] - base[s];
+  const uint64_t goff = gg * g.group_len;
+  GroupInfo r;
+  r.start = sstart + goff;
+  r.len = goff < slen ? (slen - goff < g.group_len ? slen - goff : g.group_len) : 0;
+  r.gi = 0;
+  r.seg = s;
+  r.gg = gg;
+  return r;
+}
+
+// Segmented mode: does buffer X_j of segment s (the output of its pass j;
+// X_0 = tile sort) live in the primary (final output) buffer?  Passes
+// alternate so that X_{npass} is the output.
+__device__ __forceinline__ bool seg_primary(const RunGeom &g, uint32_t s, uint32_t j) {
+  return ((g.seg.npass[s] - j) & 1u) == 0;
+}
 
 __device__ __forceinline__ GroupInfo group_of(const RunGeom &g, uint64_t gi) {
   GroupInfo r;
   r.gi = gi;
+  r.seg = 0;
+  r.gg = 0;
   const uint64_t seg = gi / g.groups_per_seg, gg = gi % g.groups_per_seg;
   const uint64_t seg_start = seg * g.seg_len;
   const uint64_t seg_len = seg_start < g.n ? (g.n - seg_start < g.seg_len ? g.n - seg_start : g.seg_len) : 0;
@@ -311,10 +386,25 @@ struct RowInfo {
   GroupInfo grp;
   uint64_t rank;
   uint32_t *out;
+  bool valid;
 };
 
 __device__ __forceinline__ RowInfo row_info(const RunGeom &g, uint64_t row, uint32_t *table) {
   RowInfo ri;
+  ri.valid = true;
+  if (g.seg.off) {
+    ri.out = table + row * g.fan;
+    if (row >= g.seg.rows[g.seg.n_segs]) {
+      ri.valid = false;
+      return ri;
+    }
+    const uint32_t sg = seg_find(g.seg.rows, g.seg.n_segs, row);
+    const uint64_t local = row - g.seg.rows[sg];
+    ri.grp = seg_group(g, sg, local / g.rows_per_group);
+    const uint64_t r = (local % g.rows_per_group) * g.part_len;
+    ri.rank = r < ri.grp.len ? r : ri.grp.len;
+    return ri;
+  }
   if (!g.paper) {
     const uint64_t gi = row / g.rows_per_group, k = row % g.rows_per_group;
     ri.grp = group_of(g, gi);
@@ -624,14 +714,19 @@ struct SampleIndex {
 
 template <typename U, int E, bool SAMPLED>
 __global__ __launch_bounds__(kCorankThreads) void corank_wave_kernel(
-    const U *__restrict__ src, RunGeom g, uint32_t *__restrict__ table,
-    U *__restrict__ pivots, uint64_t *__restrict__ counts, int kt, SampleIndex si) {
+    const U *__restrict__ src_primary, const U *__restrict__ src_alt, RunGeom g,
+    uint32_t *__restrict__ table, U *__restrict__ pivots, uint64_t *__restrict__ counts, int kt,
+    SampleIndex si) {
   __shared__ uint32_t slot_run[64 * E];
   __shared__ uint32_t cnt[2 * 64];
 
   const uint32_t lane = threadIdx.x;
   const uint64_t row = blockIdx.x;
   const RowInfo ri = row_info(g, row, table);
+  if (!ri.valid) return;
+  // segmented keys level: the input of pass q is the segment's X_{q-1}
+  const U *src = (g.seg.off && g.seg.level == 0 && !seg_primary(g, ri.grp.seg, g.seg.pass - 1))
+                     ? src_alt : src_primary;
   const uint64_t glen = ri.grp.len, R = g.run_len, r = ri.rank;
   const uint32_t nruns = glen ? (uint32_t)((glen + R - 1) / R) : 0;
   const uint32_t len = lane < nruns ? run_length(glen, R, lane) : 0u;
@@ -655,14 +750,18 @@ __global__ __launch_bounds__(kCorankThreads) void corank_wave_kernel(
         // from the merged samples (prefix counts at the chunk + the run ids
         // of the remaining < kChunk merged samples).
         jtop = kSampleLog2;
-        const GroupInfo sg = group_of(si.gs, ri.grp.gi);
+        const GroupInfo sg = g.seg.off ? seg_group(si.gs, ri.grp.seg, ri.grp.gg)
+                                       : group_of(si.gs, ri.grp.gi);
         const uint64_t ns5 = sg.len;
         // runs with at least one sample (a short last run may have none)
         const uint64_t rs = si.gs.run_len;
         const uint32_t nruns_s = ns5 ? (uint32_t)((ns5 + rs - 1) / rs) : 0u;
         const uint64_t qs[2] = {q_lo_at(kSampleLog2),
                                 (r >> kSampleLog2) < ns5 ? (r >> kSampleLog2) : ns5};
-        const uint64_t prow0 = ri.grp.gi * (uint64_t)(si.gs.rows_per_group - 1) * (kPart / kChunk);
+        const uint64_t sppg = si.gs.rows_per_group - 1;  // sample partitions per full group
+        const uint64_t prow0 =
+            (g.seg.off ? si.gs.seg.parts[ri.grp.seg] + ri.grp.gg * sppg : ri.grp.gi * sppg) *
+            (kPart / kChunk);
         uint32_t v[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
@@ -835,12 +934,37 @@ struct PartInfo {
   uint32_t size;  // keys in this partition
   uint64_t group_start, group_len, out_off;
   const uint32_t *lo_row, *hi_row;
+  uint32_t seg;   // segmented mode: segment and group within it
+  uint64_t gg;
 };
 
 __device__ __forceinline__ PartInfo part_info(const RunGeom &g, uint64_t pidx,
                                               const uint32_t *table, const uint64_t *part_off) {
   PartInfo pi;
   pi.valid = false;
+  pi.seg = 0;
+  pi.gg = 0;
+  if (g.seg.off) {
+    if (pidx >= g.seg.parts[g.seg.n_segs]) return pi;
+    const uint32_t sg = seg_find(g.seg.parts, g.seg.n_segs, pidx);
+    const uint64_t local = pidx - g.seg.parts[sg];
+    const uint64_t ppg = g.rows_per_group - 1;
+    const uint64_t gg = local / ppg, k = local % ppg;
+    const GroupInfo grp = seg_group(g, sg, gg);
+    const uint64_t rlo = k * g.part_len;
+    if (rlo >= grp.len) return pi;
+    const uint64_t rhi = rlo + g.part_len < grp.len ? rlo + g.part_len : grp.len;
+    pi.size = (uint32_t)(rhi - rlo);
+    pi.group_start = grp.start;
+    pi.group_len = grp.len;
+    pi.out_off = grp.start + rlo;
+    pi.lo_row = table + (g.seg.rows[sg] + gg * g.rows_per_group + k) * g.fan;
+    pi.hi_row = pi.lo_row + g.fan;
+    pi.seg = sg;
+    pi.gg = gg;
+    pi.valid = true;
+    return pi;
+  }
   if (!g.paper) {
     const uint32_t ppg = g.rows_per_group - 1;
     const uint64_t gi = pidx / ppg, k = pidx % ppg;
@@ -931,11 +1055,20 @@ __device__ __forceinline__ uint32_t find_segment(const uint32_t *soff, uint32_t 
 // every kChunk-th output are written to `prefix` (for the splitter search of
 // the data pass).  samples != nullptr: write every kSample-th output key of
 // each output run (run = this pass's group) for the next pass.
+// Buffers of one merge launch.  Uniform and paper modes use the primary
+// pointers only; the segmented mode picks, per segment, primary or alt by the
+// parity of the segment's remaining passes.
+template <typename U> struct MergeBufs {
+  const U *src, *src_alt;
+  const uint32_t *vsrc, *vsrc_alt;
+  U *dst, *dst_alt;
+  uint32_t *vdst, *vdst_alt;
+};
+
 template <int KT, int VMODE, uint32_t MAXF>
 __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
-    const typename Key<KT>::U *__restrict__ src, const uint32_t *__restrict__ vsrc,
-    typename Key<KT>::U *__restrict__ dst, uint32_t *__restrict__ vdst, RunGeom g,
-    const uint32_t *__restrict__ table, const uint64_t *__restrict__ part_off, int final_pass,
+    MergeBufs<typename Key<KT>::U> bufs, RunGeom g, const uint32_t *__restrict__ table,
+    const uint64_t *__restrict__ part_off, int final_pass,
     typename Key<KT>::U *__restrict__ samples, uint32_t *__restrict__ prefix) {
   using U = typename Key<KT>::U;
   constexpr bool KV = VMODE != 0;
@@ -953,6 +1086,24 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
   if (!pi.valid) return;
   const uint64_t R = g.run_len;
   const uint32_t F = (uint32_t)((pi.group_len + R - 1) / R);
+  const U *src = bufs.src;
+  const uint32_t *vsrc = bufs.vsrc;
+  U *dst = bufs.dst;
+  uint32_t *vdst = bufs.vdst;
+  bool write_samples = samples != nullptr;
+  if (g.seg.off && g.seg.level == 0) {
+    const uint32_t q = g.seg.pass;
+    if (!seg_primary(g, pi.seg, q - 1)) {
+      src = bufs.src_alt;
+      vsrc = bufs.vsrc_alt;
+    }
+    if (!seg_primary(g, pi.seg, q)) {
+      dst = bufs.dst_alt;
+      vdst = bufs.vdst_alt;
+    }
+    final_pass = g.seg.npass[pi.seg] == q;
+    write_samples = write_samples && !final_pass;
+  }
 
   for (uint32_t b = tid; b < F; b += kMergeThreads) {
     const uint32_t lo = pi.lo_row[b], hi = pi.hi_row[b];
@@ -1135,12 +1286,17 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
       if constexpr (KV) vdst[pi.out_off + idx] = sv[pad16(idx)];
     }
   }
-  if (samples != nullptr && !g.paper) {
+  if (write_samples && !g.paper) {
     // this partition starts at group position rlo, a multiple of kSample
-    const uint64_t gi = blockIdx.x / (g.rows_per_group - 1);
-    const uint64_t seg = gi / g.groups_per_seg, gg = gi % g.groups_per_seg;
     const uint64_t rlo = pi.out_off - pi.group_start;
-    const uint64_t sbase = seg * (g.seg_len >> kSampleLog2) + ((gg * g.group_len + rlo) >> kSampleLog2);
+    uint64_t sbase;
+    if (g.seg.off) {
+      sbase = g.seg.soff[pi.seg] + ((pi.gg * g.group_len + rlo) >> kSampleLog2);
+    } else {
+      const uint64_t gi = blockIdx.x / (g.rows_per_group - 1);
+      const uint64_t seg = gi / g.groups_per_seg, gg = gi % g.groups_per_seg;
+      sbase = seg * (g.seg_len >> kSampleLog2) + ((gg * g.group_len + rlo) >> kSampleLog2);
+    }
     for (uint32_t i = tid; i < (M >> kSampleLog2); i += kMergeThreads)
       samples[sbase + i] = sk[pad16((i << kSampleLog2) + kSample - 1)];
   }
@@ -1231,6 +1387,132 @@ __global__ void unmap_copy_kernel(const typename Key<KT>::U *__restrict__ src,
   if (i < n) dst[i] = Key<KT>::unmap(src[i]);
 }
 
+// ------------------------------------------------- segmented planning ---
+// One workgroup reads the segment offsets, checks them, and writes per
+// segment: its tile class and tiles, merge passes, samples, and per pass the
+// table rows and partitions at key and sample level; then turns every array
+// into an exclusive prefix over segments.  Invalid offsets (not starting at
+// 0, decreasing, or not ending at n) give an empty plan and an error bit.
+struct SegPlanArrays {
+  uint64_t *tiles[3];
+  uint64_t *soff;
+  uint32_t *npass;
+  uint64_t *rows[kMaxSegPasses], *parts[kMaxSegPasses];
+  uint64_t *srows[kMaxSegPasses], *sparts[kMaxSegPasses];
+};
+
+__device__ void block_inclusive_scan_u64(uint64_t *a, uint32_t n, uint64_t *wsum) {
+  const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+  const uint32_t lane = tid & 63, wid = tid >> 6, nw = nthr >> 6;
+  const uint32_t per = (n + nthr - 1) / nthr;
+  const uint32_t beg = tid * per < n ? tid * per : n;
+  const uint32_t end = beg + per < n ? beg + per : n;
+  uint64_t s = 0;
+  for (uint32_t i = beg; i < end; ++i) s += a[i];
+  uint64_t x = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(x, d, 64);
+    if ((int)lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wid] = x;
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t run = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+      const uint64_t v = wsum[w];
+      wsum[w] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  uint64_t e = x - s + wsum[wid];
+  for (uint32_t i = beg; i < end; ++i) {
+    e += a[i];
+    a[i] = e;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void seg_plan_kernel(const uint64_t *__restrict__ off,
+                                                        uint32_t n_segs, uint64_t n,
+                                                        SegPlanArrays pa, uint32_t small0,
+                                                        uint32_t small1, uint32_t max_passes) {
+  __shared__ uint64_t wsum[17];
+  __shared__ uint32_t bad;
+  const uint32_t tid = threadIdx.x;
+  if (tid == 0) bad = (off[0] != 0 || off[n_segs] != n) ? 1u : 0u;
+  __syncthreads();
+  for (uint32_t s = tid; s < n_segs; s += blockDim.x)
+    if (off[s + 1] < off[s]) atomicOr(&bad, 1u);
+  __syncthreads();
+  const bool ok = bad == 0;
+  if (tid == 0 && !ok) report(kErrSegments);
+  for (uint32_t s = tid; s <= n_segs; s += blockDim.x) {
+    // index s+1 holds segment s's count; index 0 stays 0 (exclusive prefix)
+    if (s == 0) {
+      for (int c = 0; c < 3; ++c) pa.tiles[c][0] = 0;
+      pa.soff[0] = 0;
+      for (uint32_t q = 0; q < max_passes; ++q) {
+        pa.rows[q][0] = 0;
+        pa.parts[q][0] = 0;
+        pa.srows[q][0] = 0;
+        pa.sparts[q][0] = 0;
+      }
+    }
+    if (s == n_segs) continue;
+    const uint64_t L = ok ? off[s + 1] - off[s] : 0;
+    int cls = L == 0 ? -1 : (L <= small0 ? 0 : (L <= small1 ? 1 : 2));
+    uint32_t np = 0;
+    if (cls == 2 && L > (uint64_t)kTile) {
+      const uint64_t tiles = (L + kTile - 1) / kTile;
+      uint32_t bits = 0;
+      while (((uint64_t)1 << bits) < tiles) ++bits;
+      np = (bits + kMaxFanLog2 - 1) / kMaxFanLog2;
+    }
+    if (np > max_passes) {  // the host bound on passes was too small
+      atomicOr(&bad, 2u);
+      np = 0;
+      cls = -1;
+    }
+    for (int c = 0; c < 3; ++c)
+      pa.tiles[c][s + 1] = c == cls ? (c == 2 ? (L + kTile - 1) / kTile : 1) : 0;
+    pa.npass[s] = np;
+    pa.soff[s + 1] = np ? (L >> kSampleLog2) : 0;
+    const uint64_t Ls = L >> kSampleLog2;
+    for (uint32_t q = 1; q <= max_passes; ++q) {
+      uint64_t rows = 0, parts = 0, srows = 0, sparts = 0;
+      if (q <= np) {
+        const uint64_t R = (uint64_t)kTile << (kMaxFanLog2 * (q - 1));
+        const uint64_t G = R << kMaxFanLog2, Gs = G >> kSampleLog2;
+        const uint64_t ng = (L + G - 1) / G;
+        for (uint64_t gg = 0; gg < ng; ++gg) {
+          const uint64_t glen = L - gg * G < G ? L - gg * G : G;
+          const uint64_t gs = gg * Gs < Ls ? (Ls - gg * Gs < Gs ? Ls - gg * Gs : Gs) : 0;
+          parts += (glen + kPart - 1) / kPart;
+          rows += (glen + kPart - 1) / kPart + 1;
+          sparts += (gs + kPart - 1) / kPart;
+          srows += (gs + kPart - 1) / kPart + 1;
+        }
+      }
+      pa.rows[q - 1][s + 1] = rows;
+      pa.parts[q - 1][s + 1] = parts;
+      pa.srows[q - 1][s + 1] = srows;
+      pa.sparts[q - 1][s + 1] = sparts;
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && (bad & 2u)) report(kErrSegments);
+  for (int c = 0; c < 3; ++c) block_inclusive_scan_u64(pa.tiles[c] + 1, n_segs, wsum);
+  block_inclusive_scan_u64(pa.soff + 1, n_segs, wsum);
+  for (uint32_t q = 0; q < max_passes; ++q) {
+    block_inclusive_scan_u64(pa.rows[q] + 1, n_segs, wsum);
+    block_inclusive_scan_u64(pa.parts[q] + 1, n_segs, wsum);
+    block_inclusive_scan_u64(pa.srows[q] + 1, n_segs, wsum);
+    block_inclusive_scan_u64(pa.sparts[q] + 1, n_segs, wsum);
+  }
+}
+
 template <typename F>
 hipError_t dispatch_kt(int kt, F &&f) {
   switch (kt) {
@@ -1260,6 +1542,17 @@ RunGeom sample_geom(const RunGeom &g) {
   return s;
 }
 
+namespace {
+template <int KT, bool KV, int THREADS>
+hipError_t go_tile(const void *in, const uint32_t *vin, const TileArgs<typename Key<KT>::U> &ta,
+                   uint64_t grid, hipStream_t s) {
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((tile_sort_kernel<KT, KV, THREADS>), dim3((uint32_t)grid), dim3(THREADS), 0, s,
+                     (const typename Key<KT>::U *)in, vin, ta);
+  return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_tile_sort(int kt, bool kv, const void *in, const uint32_t *vin, void *out,
                             uint32_t *vout, uint64_t n, uint64_t seg_len, int final_pass,
                             void *samples, hipStream_t s) {
@@ -1270,20 +1563,77 @@ hipError_t launch_tile_sort(int kt, bool kv, const void *in, const uint32_t *vin
   return dispatch_kt(kt, [&](auto ktc) {
     constexpr int KT = decltype(ktc)::value;
     using U = typename Key<KT>::U;
-    if (kv)
-      hipLaunchKernelGGL((tile_sort_kernel<KT, true>), dim3((uint32_t)grid), dim3(kTileThreads), 0, s,
-                         (const U *)in, vin, (U *)out, vout, n, seg_len, tps, final_pass, (U *)samples);
-    else
-      hipLaunchKernelGGL((tile_sort_kernel<KT, false>), dim3((uint32_t)grid), dim3(kTileThreads), 0, s,
-                         (const U *)in, vin, (U *)out, vout, n, seg_len, tps, final_pass, (U *)samples);
-    return hipGetLastError();
+    TileArgs<U> ta{};
+    ta.n = n;
+    ta.seg_len = seg_len;
+    ta.tiles_per_seg = tps;
+    ta.final_pass = final_pass;
+    ta.out = ta.out_alt = (U *)out;
+    ta.vout = ta.vout_alt = vout;
+    ta.samples = (U *)samples;
+    return kv ? go_tile<KT, true, kTileThreads>(in, vin, ta, grid, s)
+              : go_tile<KT, false, kTileThreads>(in, vin, ta, grid, s);
+  });
+}
+
+hipError_t launch_seg_plan(const uint64_t *seg_off, uint32_t n_segs, uint64_t n,
+                           const SegPlanPtrs &pp, uint32_t small0, uint32_t small1,
+                           uint32_t max_passes, hipStream_t s) {
+  SegPlanArrays pa{};
+  for (int c = 0; c < 3; ++c) pa.tiles[c] = pp.tiles[c];
+  pa.soff = pp.soff;
+  pa.npass = pp.npass;
+  for (uint32_t q = 0; q < kMaxSegPasses; ++q) {
+    pa.rows[q] = pp.rows[q];
+    pa.parts[q] = pp.parts[q];
+    pa.srows[q] = pp.srows[q];
+    pa.sparts[q] = pp.sparts[q];
+  }
+  hipLaunchKernelGGL(seg_plan_kernel, dim3(1), dim3(1024), 0, s, seg_off, n_segs, n, pa, small0,
+                     small1, max_passes);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_tile_sorts(int kt, bool kv, const void *in, const uint32_t *vin, void *out,
+                                 void *out_alt, uint32_t *vout, uint32_t *vout_alt, void *samples,
+                                 const uint64_t *seg_off, const SegPlanPtrs &pp, uint32_t n_segs,
+                                 uint64_t n, hipStream_t s) {
+  return dispatch_kt(kt, [&](auto ktc) {
+    constexpr int KT = decltype(ktc)::value;
+    using U = typename Key<KT>::U;
+    TileArgs<U> ta{};
+    ta.out = (U *)out;
+    ta.out_alt = (U *)out_alt;
+    ta.vout = vout;
+    ta.vout_alt = vout_alt;
+    ta.samples = (U *)samples;
+    ta.seg_off = seg_off;
+    ta.soff = pp.soff;
+    ta.npass = pp.npass;
+    ta.n_segs = n_segs;
+    hipError_t e;
+    // class 0: one 2048-key tile per segment; class 1: one 4096-key tile;
+    // class 2: tiles of kTile keys
+    ta.tiles = pp.tiles[0];
+    e = kv ? go_tile<KT, true, kSmallThreads0>(in, vin, ta, n_segs, s)
+           : go_tile<KT, false, kSmallThreads0>(in, vin, ta, n_segs, s);
+    if (e != hipSuccess) return e;
+    ta.tiles = pp.tiles[1];
+    e = kv ? go_tile<KT, true, kSmallThreads1>(in, vin, ta, n_segs, s)
+           : go_tile<KT, false, kSmallThreads1>(in, vin, ta, n_segs, s);
+    if (e != hipSuccess) return e;
+    ta.tiles = pp.tiles[2];
+    const uint64_t grid = (n + kTile - 1) / kTile + n_segs;
+    return kv ? go_tile<KT, true, kTileThreads>(in, vin, ta, grid, s)
+              : go_tile<KT, false, kTileThreads>(in, vin, ta, grid, s);
   });
 }
 
 hipError_t launch_corank(int kt, const void *src, const RunGeom &g, uint32_t *table,
-                         void *pivots, uint64_t *counts, hipStream_t s) {
+                         void *pivots, uint64_t *counts, hipStream_t s, const void *src_alt) {
   const uint64_t rows = g.total_rows();
   if (rows == 0) return hipSuccess;
+  if (!src_alt) src_alt = src;
   auto go = [&](auto u, auto maxf) -> hipError_t {
     using U = decltype(u);
     constexpr uint32_t MAXF = decltype(maxf)::value;
@@ -1296,14 +1646,15 @@ hipError_t launch_corank(int kt, const void *src, const RunGeom &g, uint32_t *ta
     const SampleIndex none{nullptr, nullptr, g};
     if (wide)
       hipLaunchKernelGGL((corank_wave_kernel<uint64_t, 4, false>), dim3((uint32_t)rows),
-                         dim3(kCorankThreads), 0, s, (const uint64_t *)src, g, table,
-                         (uint64_t *)pivots, counts, kt, none);
+                         dim3(kCorankThreads), 0, s, (const uint64_t *)src, (const uint64_t *)src_alt,
+                         g, table, (uint64_t *)pivots, counts, kt, none);
     else
       hipLaunchKernelGGL((corank_wave_kernel<uint32_t, 4, false>), dim3((uint32_t)rows),
-                         dim3(kCorankThreads), 0, s, (const uint32_t *)src, g, table,
-                         (uint32_t *)pivots, counts, kt, none);
+                         dim3(kCorankThreads), 0, s, (const uint32_t *)src, (const uint32_t *)src_alt,
+                         g, table, (uint32_t *)pivots, counts, kt, none);
     return hipGetLastError();
   }
+  if (g.seg.off) return hipErrorInvalidValue;
   if (g.fan <= 512)
     return wide ? go(uint64_t{}, std::integral_constant<uint32_t, 512>{})
                 : go(uint32_t{}, std::integral_constant<uint32_t, 512>{});
@@ -1315,56 +1666,64 @@ hipError_t launch_corank(int kt, const void *src, const RunGeom &g, uint32_t *ta
 
 hipError_t launch_corank_sampled(int kt, const void *src, const RunGeom &g, uint32_t *table,
                                  const uint32_t *sample_runs, const uint32_t *sample_prefix,
-                                 hipStream_t s) {
+                                 hipStream_t s, const void *src_alt, const RunGeom *gs_in) {
   const uint64_t rows = g.total_rows();
   if (rows == 0) return hipSuccess;
   if (g.fan > kMaxSampledFan || g.paper) return hipErrorInvalidValue;
-  const SampleIndex si{sample_runs, sample_prefix, sample_geom(g)};
+  if (!src_alt) src_alt = src;
+  const SampleIndex si{sample_runs, sample_prefix, gs_in ? *gs_in : sample_geom(g)};
   if (key_bytes(kt) == 8)
     hipLaunchKernelGGL((corank_wave_kernel<uint64_t, 4, true>), dim3((uint32_t)rows),
-                       dim3(kCorankThreads), 0, s, (const uint64_t *)src, g, table,
-                       (uint64_t *)nullptr, (uint64_t *)nullptr, kt, si);
+                       dim3(kCorankThreads), 0, s, (const uint64_t *)src, (const uint64_t *)src_alt,
+                       g, table, (uint64_t *)nullptr, (uint64_t *)nullptr, kt, si);
   else
     hipLaunchKernelGGL((corank_wave_kernel<uint32_t, 4, true>), dim3((uint32_t)rows),
-                       dim3(kCorankThreads), 0, s, (const uint32_t *)src, g, table,
-                       (uint32_t *)nullptr, (uint64_t *)nullptr, kt, si);
+                       dim3(kCorankThreads), 0, s, (const uint32_t *)src, (const uint32_t *)src_alt,
+                       g, table, (uint32_t *)nullptr, (uint64_t *)nullptr, kt, si);
   return hipGetLastError();
 }
 
 hipError_t launch_merge(int kt, int vmode, const void *src, const uint32_t *vsrc, void *dst,
                         uint32_t *vdst, const RunGeom &g, const uint32_t *table,
                         const uint64_t *part_offsets, int final_pass, void *samples,
-                        uint32_t *prefix, hipStream_t s) {
+                        uint32_t *prefix, hipStream_t s, const MergeAlt *alt) {
   const uint64_t parts = g.total_parts();
   if (parts == 0) return hipSuccess;
   if (vmode == 2) {
     // sample arrays hold mapped keys: merge them as plain unsigned integers
     if (g.fan > kMaxSampledFan || final_pass || samples) return hipErrorInvalidValue;
-    if (key_bytes(kt) == 8)
-      hipLaunchKernelGGL((merge_kernel<2, 2, 64>), dim3((uint32_t)parts), dim3(kMergeThreads), 0, s,
-                         (const uint64_t *)src, vsrc, (uint64_t *)dst, vdst, g, table, part_offsets,
-                         0, (uint64_t *)nullptr, prefix);
-    else
-      hipLaunchKernelGGL((merge_kernel<0, 2, 64>), dim3((uint32_t)parts), dim3(kMergeThreads), 0, s,
-                         (const uint32_t *)src, vsrc, (uint32_t *)dst, vdst, g, table, part_offsets,
-                         0, (uint32_t *)nullptr, prefix);
-    return hipGetLastError();
+    auto go2 = [&](auto u) -> hipError_t {
+      using U = decltype(u);
+      constexpr int KTI = sizeof(U) == 8 ? 2 : 0;
+      MergeBufs<U> b{(const U *)src, (const U *)src, vsrc, vsrc, (U *)dst, (U *)dst, vdst, vdst};
+      hipLaunchKernelGGL((merge_kernel<KTI, 2, 64>), dim3((uint32_t)parts), dim3(kMergeThreads), 0, s,
+                         b, g, table, part_offsets, 0, (U *)nullptr, prefix);
+      return hipGetLastError();
+    };
+    return key_bytes(kt) == 8 ? go2(uint64_t{}) : go2(uint32_t{});
   }
   return dispatch_kt(kt, [&](auto ktc) {
     constexpr int KT = decltype(ktc)::value;
     using U = typename Key<KT>::U;
+    MergeBufs<U> b{(const U *)src, (const U *)src, vsrc, vsrc, (U *)dst, (U *)dst, vdst, vdst};
+    if (alt) {
+      b.src_alt = (const U *)alt->src;
+      b.vsrc_alt = alt->vsrc;
+      b.dst_alt = (U *)alt->dst;
+      b.vdst_alt = alt->vdst;
+    }
     auto go = [&](auto vm, auto maxf) -> hipError_t {
       constexpr int VM = decltype(vm)::value;
       constexpr uint32_t MAXF = decltype(maxf)::value;
       hipLaunchKernelGGL((merge_kernel<KT, VM, MAXF>), dim3((uint32_t)parts), dim3(kMergeThreads), 0, s,
-                         (const U *)src, vsrc, (U *)dst, vdst, g, table, part_offsets, final_pass,
-                         (U *)samples, (uint32_t *)nullptr);
+                         b, g, table, part_offsets, final_pass, (U *)samples, (uint32_t *)nullptr);
       return hipGetLastError();
     };
     const bool kv = vmode == 1;
     if (g.fan <= 64)
       return kv ? go(std::integral_constant<int, 1>{}, std::integral_constant<uint32_t, 64>{})
                 : go(std::integral_constant<int, 0>{}, std::integral_constant<uint32_t, 64>{});
+    if (g.seg.off) return hipErrorInvalidValue;
     if (g.fan <= kMaxRuns)
       return kv ? go(std::integral_constant<int, 1>{}, std::integral_constant<uint32_t, kMaxRuns>{})
                 : go(std::integral_constant<int, 0>{}, std::integral_constant<uint32_t, kMaxRuns>{});

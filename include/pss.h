@@ -168,9 +168,10 @@ pss_status pss_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, uint6
  * and every later kernel finds its segment through the plan's prefix tables.
  *
  *   seg_offsets: DEVICE array of n_segs + 1 uint64, seg_offsets[0] = 0,
- *     non-decreasing, seg_offsets[n_segs] = n.  Invalid offsets leave the
- *     output unspecified and set bit 16 of the device error word
- *     (pss_device_check).
+ *     non-decreasing, seg_offsets[n_segs] <= n (keys past the last offset are
+ *     left alone, so a batch may fill a buffer sized for n only partly, with
+ *     unused trailing segments empty).  Invalid offsets leave the output
+ *     unspecified and set bit 16 of the device error word (pss_device_check).
  *   tuning (host, may be NULL = defaults): which segments go to the smaller
  *     tile sorts, and a bound on the longest segment that bounds the number
  *     of merge passes launched.  Chosen by the project's autotuner per
@@ -193,6 +194,25 @@ pss_status pss_segmented_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const 
                               void *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
                               uint64_t n, const uint64_t *seg_offsets, uint32_t n_segs,
                               const pss_tuning *tuning, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Capture the launch sequence of one pss_segmented_sort call (same arguments,
+ * no stream) into an instantiated HIP graph.  pss_graph_launch replays it on
+ * `stream`: the same kernels on the same buffers, reading whatever keys,
+ * values and offsets those buffers then hold, so one graph serves every batch
+ * of at most n keys in at most n_segs segments (pad unused trailing offsets
+ * with the batch total).  The graph holds no memset nodes.  The caller keeps
+ * every buffer alive while the graph exists.
+ */
+typedef struct pss_graph pss_graph;
+pss_status pss_segmented_graph_create(pss_ctx *ctx, pss_key_t key, pss_val_t val,
+                                      const void *keys_in, void *keys_out,
+                                      const uint32_t *vals_in, uint32_t *vals_out, uint64_t n,
+                                      const uint64_t *seg_offsets, uint32_t n_segs,
+                                      const pss_tuning *tuning, void *ws, size_t ws_bytes,
+                                      pss_graph **out);
+pss_status pss_graph_launch(pss_graph *graph, void *stream);
+void pss_graph_destroy(pss_graph *graph);
 
 /*
  * Per-launch timing for measurement.  While enabled, every kernel launch that

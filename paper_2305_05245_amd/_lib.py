@@ -35,6 +35,10 @@ SIGNATURES = {
     "pss_plan_describe": (_int, [_int, _int, _u64, _u32, _u32, _c.c_char_p, _sz]),
     "pss_sort": (_int, [_vp, _int, _int, _vp, _vp, _vp, _vp, _u64, _u32, _u32, _vp, _sz, _vp]),
     "pss_device_check": (_int, [_vp, _c.POINTER(_u32)]),
+    "pss_segmented_graph_create": (_int, [_vp, _int, _int, _vp, _vp, _vp, _vp, _u64, _vp, _u32,
+                                          _vp, _vp, _sz, _c.POINTER(_vp)]),
+    "pss_graph_launch": (_int, [_vp, _vp]),
+    "pss_graph_destroy": (None, [_vp]),
     "pss_segmented_workspace_bytes": (_int, [_vp, _int, _int, _u64, _u32, _vp, _c.POINTER(_sz)]),
     "pss_segmented_sort": (_int, [_vp, _int, _int, _vp, _vp, _vp, _vp, _u64, _vp, _u32, _vp, _vp,
                                   _sz, _vp]),
@@ -126,6 +130,28 @@ def segmented_workspace_bytes(key: int, val: int, n: int, n_segs: int,
     return int(out.value)
 
 
+class Graph:
+    """An instantiated HIP graph of one segmented-sort launch sequence."""
+
+    def __init__(self, lib, handle):
+        self.lib = lib
+        self.handle = handle
+
+    def launch(self, stream: int) -> None:
+        check(self.lib.pss_graph_launch(self.handle, stream or None))
+
+    def close(self) -> None:
+        if self.handle:
+            self.lib.pss_graph_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """One pss_ctx bound to a HIP device."""
 
@@ -168,6 +194,17 @@ class Context:
                                           vals_in or None, vals_out or None, n, seg_offsets or None,
                                           n_segs, ctypes.byref(tuning) if tuning else None,
                                           ws or None, ws_bytes, stream or None), self.handle)
+
+    def segmented_graph(self, key: int, val: int, keys_in: int, keys_out: int, vals_in: int,
+                        vals_out: int, n: int, seg_offsets: int, n_segs: int,
+                        tuning: Tuning | None, ws: int, ws_bytes: int) -> "Graph":
+        h = ctypes.c_void_p()
+        check(self.lib.pss_segmented_graph_create(
+            self.handle, key, val, keys_in or None, keys_out or None, vals_in or None,
+            vals_out or None, n, seg_offsets or None, n_segs,
+            ctypes.byref(tuning) if tuning else None, ws or None, ws_bytes, ctypes.byref(h)),
+            self.handle)
+        return Graph(self.lib, h)
 
     def device_check(self) -> int:
         """Synchronise the device and return (and clear) the error word."""

@@ -718,6 +718,82 @@ pss_status pss_segmented_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const 
   return PSS_OK;
 }
 
+struct pss_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+};
+
+pss_status pss_segmented_graph_create(pss_ctx *ctx, pss_key_t key, pss_val_t val,
+                                      const void *keys_in, void *keys_out,
+                                      const uint32_t *vals_in, uint32_t *vals_out, uint64_t n,
+                                      const uint64_t *seg_offsets, uint32_t n_segs,
+                                      const pss_tuning *tuning, void *ws, size_t ws_bytes,
+                                      pss_graph **out) {
+  if (!out) return fail(ctx, PSS_ERR_INVALID, "null output handle");
+  *out = nullptr;
+  if (!ctx) return fail(nullptr, PSS_ERR_INVALID, "null context");
+  PSS_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t cs = nullptr;
+  PSS_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+  const bool prof = ctx->profiling;
+  ctx->profiling = false;  // no timing events inside a captured graph
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  pss_status st = PSS_OK;
+  if (e == hipSuccess) {
+    st = pss_segmented_sort(ctx, key, val, keys_in, keys_out, vals_in, vals_out, n, seg_offsets,
+                            n_segs, tuning, ws, ws_bytes, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (st == PSS_OK && e2 != hipSuccess) {
+      ctx->profiling = prof;
+      hipStreamDestroy(cs);
+      return hip_fail(ctx, e2, "hipStreamEndCapture");
+    }
+    ctx->profiling = prof;
+    if (st != PSS_OK) {
+      if (g) hipGraphDestroy(g);
+      hipStreamDestroy(cs);
+      return st;
+    }
+    pss_graph *pg = new (std::nothrow) pss_graph;
+    if (!pg) {
+      hipGraphDestroy(g);
+      hipStreamDestroy(cs);
+      return fail(ctx, PSS_ERR_OOM, "out of host memory");
+    }
+    pg->graph = g;
+    pg->device = ctx->device;
+    e = hipGraphInstantiate(&pg->exec, g, nullptr, nullptr, 0);
+    hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+      hipGraphDestroy(g);
+      delete pg;
+      return hip_fail(ctx, e, "hipGraphInstantiate");
+    }
+    *out = pg;
+    return PSS_OK;
+  }
+  ctx->profiling = prof;
+  hipStreamDestroy(cs);
+  return hip_fail(ctx, e, "hipStreamBeginCapture");
+}
+
+pss_status pss_graph_launch(pss_graph *g, void *stream) {
+  if (!g || !g->exec) return fail(nullptr, PSS_ERR_INVALID, "null graph");
+  hipError_t e = hipSetDevice(g->device);
+  if (e == hipSuccess) e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGraphLaunch");
+  return PSS_OK;
+}
+
+void pss_graph_destroy(pss_graph *g) {
+  if (!g) return;
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  delete g;
+}
+
 pss_status pss_device_check(pss_ctx *ctx, uint32_t *code) {
   if (!ctx || !code) return fail(ctx, PSS_ERR_INVALID, "null argument");
   PSS_TRY(hipSetDevice(ctx->device), "hipSetDevice");

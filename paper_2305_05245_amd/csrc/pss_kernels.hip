@@ -1392,7 +1392,7 @@ __global__ void unmap_copy_kernel(const typename Key<KT>::U *__restrict__ src,
 // segment: its tile class and tiles, merge passes, samples, and per pass the
 // table rows and partitions at key and sample level; then turns every array
 // into an exclusive prefix over segments.  Invalid offsets (not starting at
-// 0, decreasing, or not ending at n) give an empty plan and an error bit.
+// 0, decreasing, or ending beyond n) give an empty plan and an error bit.
 struct SegPlanArrays {
   uint64_t *tiles[3];
   uint64_t *soff;
@@ -1441,7 +1441,7 @@ __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint64_t *__restri
   __shared__ uint64_t wsum[17];
   __shared__ uint32_t bad;
   const uint32_t tid = threadIdx.x;
-  if (tid == 0) bad = (off[0] != 0 || off[n_segs] != n) ? 1u : 0u;
+  if (tid == 0) bad = (off[0] != 0 || off[n_segs] > n) ? 1u : 0u;
   __syncthreads();
   for (uint32_t s = tid; s < n_segs; s += blockDim.x)
     if (off[s + 1] < off[s]) atomicOr(&bad, 1u);

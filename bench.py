@@ -16,6 +16,8 @@ sequential oracle timed on a bounded sample on the host.
 from __future__ import annotations
 
 import argparse
+import collections
+import ctypes
 import json
 import os
 import sys
@@ -82,6 +84,190 @@ def cpu_baseline(log2n: int = 25):
                       f"{dt:.1f} s"}
 
 
+def bench_batched(pss, torch, steps: int, warmup: int) -> dict:
+    """4096 int64 arrays of round(2^U) keys, U ~ Uniform[6, 20] (seed 12), keys
+    uniform over the full range (seed 13): the segmented sort replayed from one
+    captured HIP graph, against one pss_sort launch sequence per array on the
+    same stream.  Both outputs must agree bit for bit."""
+    import numpy as np
+
+    import workloads as W
+    from paper_2305_05245_amd import _lib, _context, autotune
+
+    sizes = W.segment_sizes_loguniform(4096, 6.0, 20.0, seed=12)
+    offs = W.segment_offsets(sizes).astype(np.int64)
+    total, n_segs = int(offs[-1]), sizes.size
+    keys = torch.from_numpy(W.uniform_i64(total, seed=13)).cuda()
+    out = torch.empty_like(keys)
+    d_offs = torch.from_numpy(offs).cuda()
+    best = autotune.cached(_lib.I64, _lib.VAL_NONE, total, n_segs)
+    source = "cache"
+    if best is None:
+        best = autotune.tune(_lib.I64, _lib.VAL_NONE, total, n_segs, reps=2, store=False)
+        source = "tuned now"
+    tu = _lib.Tuning(int(best["small_max_2k"]), int(best["small_max_4k"]), int(sizes.max()))
+    ws = torch.empty(_lib.segmented_workspace_bytes(_lib.I64, _lib.VAL_NONE, total, n_segs, tu),
+                     dtype=torch.uint8, device="cuda")
+    ctx = _context(0)
+    graph = ctx.segmented_graph(_lib.I64, _lib.VAL_NONE, keys.data_ptr(), out.data_ptr(), 0, 0,
+                                total, d_offs.data_ptr(), n_segs, tu, ws.data_ptr(), ws.numel())
+    stream = torch.cuda.current_stream()
+    h = stream.cuda_stream
+    for _ in range(warmup):
+        graph.launch(h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.launch(h)
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / steps
+    del ws
+
+    out2 = torch.empty_like(keys)
+    sws = torch.empty(_lib.workspace_bytes(_lib.I64, _lib.VAL_NONE, int(sizes.max())),
+                      dtype=torch.uint8, device="cuda")
+    kp, op, wp, wn = keys.data_ptr(), out2.data_ptr(), sws.data_ptr(), sws.numel()
+    plist = [(int(o) * 8, int(n)) for o, n in zip(offs[:-1], sizes)]
+
+    def per_array():
+        for o, n in plist:
+            ctx.sort(_lib.I64, _lib.VAL_NONE, kp + o, op + o, 0, 0, n, 0, 0, wp, wn, h)
+
+    per_array()
+    torch.cuda.synchronize()
+    reps = max(2, steps // 3)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        per_array()
+    torch.cuda.synchronize()
+    t_each = (time.perf_counter() - t0) / reps
+    same = bool(torch.equal(out, out2))
+    graph.close()
+    return {"workload": "4096 int64 arrays, sizes round(2^U), U~Uniform[6,20] (seed 12), "
+                        "uniform keys (seed 13)",
+            "total_keys": total, "graph_ms": round(t_graph * 1e3, 3),
+            "graph_gkeys_per_s": round(total / t_graph / 1e9, 3),
+            "per_array_ms": round(t_each * 1e3, 3),
+            "per_array_gkeys_per_s": round(total / t_each / 1e9, 3),
+            "speedup_vs_per_array": round(t_each / t_graph, 2),
+            "tuning": {"small_max_2k": tu.small_max_2k, "small_max_4k": tu.small_max_4k,
+                       "source": source},
+            "outputs_identical": same}
+
+
+def bench_serving(torch, capacity_hint: float, n_req: int = 20000, warm_req: int = 2000,
+                  budget: int = 64 << 30, streams: int = 4) -> dict:
+    """Open-loop serving run: Poisson arrivals (seed 14), lognormal sizes with
+    median 2^16 and sigma 1.5 clipped to [2^10, 2^24] (seed 15), half the
+    requests uniform u64 keys and half keys in {0, 1, 2} (seed 16), each with
+    its uint32 input index as value, against a server holding a 64 GB budget.
+    The offered load is 0.7 x the server's own saturated throughput, measured
+    first by a closed-loop burst of the same request mix."""
+    import numpy as np
+
+    import workloads as W
+    from paper_2305_05245_amd import _lib
+    from paper_2305_05245_amd.serving import Server
+
+    hi = 1 << 24
+    pool_len = 1 << 26
+    pool_u = torch.from_numpy(W.uniform_u64(pool_len, seed=16).view(np.int64)).cuda()
+    pool_d = torch.from_numpy((W.uniform_u64(pool_len, seed=17) % np.uint64(3)).view(np.int64)).cuda()
+    idx = torch.arange(hi, dtype=torch.int32, device="cuda")
+    ring_len = 1 << 30
+    ring_k = torch.empty(ring_len, dtype=torch.int64, device="cuda")
+    ring_v = torch.empty(ring_len, dtype=torch.int32, device="cuda")
+
+    def mix(count, rate, seed_base):
+        arr, sizes, dup = W.serving_requests(count, rate, seed_arrival=14 + seed_base,
+                                             seed_size=15 + seed_base, seed_keys=16 + seed_base)
+        starts = np.random.default_rng(18 + seed_base).integers(0, pool_len - sizes + 1)
+        return arr, sizes.tolist(), dup.tolist(), starts.tolist()
+
+    srv = Server(budget, streams)
+    lib, hsrv = srv.lib, srv.handle
+    req = _lib.Request()
+    req.key, req.val = _lib.U64, _lib.VAL_U32
+    tk = ctypes.c_uint64()
+    st = ctypes.c_int()
+    pu, pd, pv = pool_u.data_ptr(), pool_d.data_ptr(), idx.data_ptr()
+    rk, rv = ring_k.data_ptr(), ring_v.data_ptr()
+
+    def drive(arrivals, sizes, dup, starts, t0_ns, reset_at=-1):
+        """Submit every request at its arrival time (busy wait); outputs go to
+        a ring that waits for the oldest request before reusing its space."""
+        outstanding = collections.deque()  # (ticket, ring start, ring end)
+        head = 0
+        late = 0
+        for j in range(len(sizes)):
+            if j == reset_at:
+                srv.reset_stats()
+                late = 0
+            n = sizes[j]
+            if head + n > ring_len:
+                head = 0
+            while outstanding and (outstanding[0][1] < head + n and head < outstanding[0][2]
+                                   or len(outstanding) > 60000):
+                lib.pss_wait(hsrv, outstanding.popleft()[0], ctypes.byref(st))
+            due = t0_ns + int(arrivals[j] * 1e9) if arrivals is not None else 0
+            if due:
+                now = time.monotonic_ns()
+                if now > due + 1_000_000:
+                    late += 1
+                while time.monotonic_ns() < due:
+                    pass
+            base = (pd if dup[j] else pu) + starts[j] * 8
+            req.keys_in, req.keys_out = base, rk + head * 8
+            req.vals_in, req.vals_out = pv, rv + head * 4
+            req.n, req.arrival_ns = n, due
+            s = lib.pss_submit(hsrv, ctypes.byref(req), ctypes.byref(tk))
+            if s != _lib.OK:
+                raise _lib.PssError(s, _lib.last_error())
+            outstanding.append((tk.value, head, head + n))
+            head += n
+        while outstanding:
+            lib.pss_wait(hsrv, outstanding.popleft()[0], ctypes.byref(st))
+            if st.value != _lib.OK:
+                raise _lib.PssError(st.value, "request failed")
+        return late
+
+    try:
+        # saturated throughput: a closed-loop burst of the same mix
+        _, sizes, dup, starts = mix(3000, 1.0, 100)
+        drive(None, sizes[:300], dup, starts, 0)
+        srv.reset_stats()
+        t0 = time.perf_counter()
+        drive(None, sizes, dup, starts, 0)
+        sat = srv.stats()
+        sat_wall = time.perf_counter() - t0
+        capacity = sum(sizes) / sat_wall
+        mean_size = float(np.mean(sizes))
+        rate = 0.7 * capacity / mean_size
+        arr, sizes, dup, starts = mix(warm_req + n_req, rate, 0)
+        t0_ns = time.monotonic_ns() + 5_000_000
+        warm_end = arr[warm_req - 1]
+        # one schedule: the counters restart when the first measured request
+        # arrives (warm-up requests still in flight then are counted too)
+        late = drive(arr, sizes, dup, starts, t0_ns, reset_at=warm_req)
+        s = srv.stats()
+    finally:
+        srv.close()
+    return {"workload": "Poisson arrivals (seed 14), lognormal sizes median 2^16 sigma 1.5 "
+                        "clipped [2^10, 2^24] (seed 15), u64 keys 50% uniform / 50% {0,1,2} "
+                        "(seed 16), u32 value = input index, budget 64 GB, 4 streams",
+            "requests": n_req, "warmup_requests": warm_req,
+            "offered_rate_req_per_s": round(rate, 1),
+            "offered_gkeys_per_s": round(rate * mean_size / 1e9, 3),
+            "saturated_gkeys_per_s": round(capacity / 1e9, 3),
+            "saturated_mean_batch_requests": round(sat["mean_batch_requests"], 1),
+            "keys_per_s": s["keys_per_s"], "gkeys_per_s": round(s["keys_per_s"] / 1e9, 3),
+            "p50_ms": round(s["latency_p50_ms"], 4), "p99_ms": round(s["latency_p99_ms"], 4),
+            "mean_ms": round(s["latency_mean_ms"], 4), "max_ms": round(s["latency_max_ms"], 4),
+            "batches": s["batches"], "mean_batch_requests": round(s["mean_batch_requests"], 2),
+            "completed": s["completed"], "late_submissions": late,
+            "warmup_end_s": round(float(warm_end), 3)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +278,9 @@ def main() -> int:
     ap.add_argument("--all-dists", action="store_true",
                     help="also time the other four int64 distributions")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 4096-array batch")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a plain device-to-device copy of the keys (bandwidth and "
                          "counter calibration), print its line and exit")
@@ -201,7 +390,19 @@ def main() -> int:
             w, _, _ = time_sort(pss, torch, keys_dev, out, ws, max(3, args.steps // 2), 1, False)
             per[name] = round(n / (w / max(3, args.steps // 2)) / 1e9, 3)
         line["distributions_gkeys_per_s"] = per
+    del keys, keys_dev, out, ws
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        print("[bench] batched segmented sort", file=sys.stderr, flush=True)
+        line["batched"] = bench_batched(pss, torch, max(3, args.steps // 2), 1)
+        torch.cuda.empty_cache()
+    if not args.no_serving:
+        print("[bench] serving loop", file=sys.stderr, flush=True)
+        line["serving"] = bench_serving(torch, 0.0, n_req=args.serve_requests,
+                                        warm_req=max(1, args.serve_requests // 10))
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
+        print("[bench] oracle on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
     return 0

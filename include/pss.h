@@ -67,7 +67,10 @@ typedef enum {
   PSS_ERR_UNSUPPORTED = 2, /* valid request outside this build's limits       */
   PSS_ERR_OOM = 3,         /* host allocation failed                          */
   PSS_ERR_HIP = 4,         /* a HIP runtime call failed (see pss_last_error)  */
-  PSS_ERR_WORKSPACE = 5    /* workspace missing or smaller than required      */
+  PSS_ERR_WORKSPACE = 5,   /* workspace missing or smaller than required      */
+  PSS_ERR_BUDGET = 6,      /* request larger than the server's memory budget  */
+  PSS_ERR_BUSY = 7,        /* request already launched: it can't be cancelled */
+  PSS_ERR_CANCELLED = 8    /* request cancelled before it was launched        */
 } pss_status;
 
 typedef struct pss_ctx pss_ctx;
@@ -213,6 +216,86 @@ pss_status pss_segmented_graph_create(pss_ctx *ctx, pss_key_t key, pss_val_t val
                                       pss_graph **out);
 pss_status pss_graph_launch(pss_graph *graph, void *stream);
 void pss_graph_destroy(pss_graph *graph);
+
+/*
+ * Serving loop.  A server sorts independent requests (each one array of keys,
+ * optionally with uint32 values, sorted ascending and stably, exactly as
+ * pss_sort would) that arrive at any time from any host thread.  Requests
+ * wait in one first-come-first-served queue.  Each of max_streams workers owns
+ * a HIP stream and an equal share of the server's device-memory budget; a
+ * worker that is free takes, in arrival order, every waiting request of the
+ * head request's key and value types that still fits its share (continuous
+ * batching: the batch is whatever arrived while the workers were busy), and
+ * sorts the batch with one segmented sort (one segment per request): a
+ * gather kernel copies the requests' inputs into the batch buffer, the
+ * segmented sort runs (step 1 in tiles, steps 2-4 per request), and a
+ * scatter kernel copies every sorted segment to its request's outputs.  The
+ * workers' streams overlap one batch's work with the next.
+ *
+ *   hbm_budget_bytes: all device memory the server holds (batch buffers,
+ *     workspace, tables), allocated at creation and split evenly over the
+ *     workers.  A request whose batch of one would not fit a worker's share
+ *     is refused at submission with PSS_ERR_BUDGET.
+ *   max_streams: workers (and streams), 1..16.
+ *   tuning (host, may be NULL): small-segment tile choice as for
+ *     pss_segmented_sort; max_seg_len is ignored (each batch uses its longest
+ *     request).
+ *
+ * pss_request (host struct, copied at submission):
+ *   keys_in, keys_out, vals_in, vals_out: DEVICE pointers owned by the caller,
+ *     naturally aligned, n elements each (values only with PSS_VAL_U32), kept
+ *     alive and unmodified until the request completes; out must not overlap
+ *     in.  n <= PSS_MAX_KEYS; n = 0 completes at once.
+ *   arrival_ns: CLOCK_MONOTONIC time of arrival in ns, the start of the
+ *     request's latency; 0 = the time of submission.
+ * Results are visible to any stream once pss_poll or pss_wait reports the
+ * request done (the worker has synchronised its stream).
+ *
+ * pss_submit never blocks on the GPU and returns a ticket (> 0).  pss_poll
+ * reports whether a ticket is done; pss_wait blocks until it is.  Both give
+ * the request's status (PSS_OK, PSS_ERR_CANCELLED, or the error of its batch)
+ * and, once they report done, forget the ticket (PSS_ERR_INVALID afterwards).
+ * pss_cancel withdraws a request that is still queued (it then completes
+ * with PSS_ERR_CANCELLED) and returns PSS_ERR_BUSY for one already launched
+ * or finished.  pss_server_stats reports counters and, over requests
+ * completed since creation or the last pss_server_reset_stats, the latency
+ * (arrival to completion) percentiles and keys/s (keys completed divided by
+ * the time from the first arrival to the last completion).
+ * pss_server_destroy cancels queued requests, waits for launched batches and
+ * frees everything; no other call on the server may be in progress.
+ * Every server call is thread-safe.  Error messages go to the calling
+ * thread's pss_last_error(NULL).
+ */
+typedef struct pss_server pss_server;
+
+typedef struct {
+  pss_key_t key;
+  pss_val_t val;
+  const void *keys_in;
+  void *keys_out;
+  const uint32_t *vals_in;
+  uint32_t *vals_out;
+  uint64_t n;
+  uint64_t arrival_ns;
+} pss_request;
+
+typedef struct {
+  uint64_t submitted, completed, rejected, cancelled, failed;
+  uint64_t batches, keys_completed;
+  double keys_per_s;
+  double latency_p50_ms, latency_p99_ms, latency_mean_ms, latency_max_ms;
+  double mean_batch_requests, mean_batch_keys;
+} pss_stats;
+
+pss_status pss_server_create(pss_ctx *ctx, size_t hbm_budget_bytes, uint32_t max_streams,
+                             const pss_tuning *tuning, pss_server **out);
+pss_status pss_submit(pss_server *server, const pss_request *req, uint64_t *ticket);
+pss_status pss_poll(pss_server *server, uint64_t ticket, int *done, pss_status *result);
+pss_status pss_wait(pss_server *server, uint64_t ticket, pss_status *result);
+pss_status pss_cancel(pss_server *server, uint64_t ticket);
+pss_status pss_server_stats(pss_server *server, pss_stats *out);
+pss_status pss_server_reset_stats(pss_server *server);
+void pss_server_destroy(pss_server *server);
 
 /*
  * Per-launch timing for measurement.  While enabled, every kernel launch that

@@ -20,7 +20,32 @@ KEY_BYTES = {U32: 4, I32: 4, U64: 8, I64: 8, F32: 4, F64: 8}
 # pss_val_t
 VAL_NONE, VAL_U32 = 0, 1
 # pss_status
-OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_OOM, ERR_HIP, ERR_WORKSPACE = range(6)
+(OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_OOM, ERR_HIP, ERR_WORKSPACE, ERR_BUDGET, ERR_BUSY,
+ ERR_CANCELLED) = range(9)
+
+
+
+class Request(ctypes.Structure):
+    """pss_request (include/pss.h): one serving request, device pointers."""
+
+    _fields_ = [("key", ctypes.c_int), ("val", ctypes.c_int), ("keys_in", ctypes.c_void_p),
+                ("keys_out", ctypes.c_void_p), ("vals_in", ctypes.c_void_p),
+                ("vals_out", ctypes.c_void_p), ("n", ctypes.c_uint64),
+                ("arrival_ns", ctypes.c_uint64)]
+
+
+class Stats(ctypes.Structure):
+    """pss_stats (include/pss.h)."""
+
+    _fields_ = [(f, ctypes.c_uint64) for f in ("submitted", "completed", "rejected", "cancelled",
+                                               "failed", "batches", "keys_completed")] + \
+               [(f, ctypes.c_double) for f in ("keys_per_s", "latency_p50_ms", "latency_p99_ms",
+                                               "latency_mean_ms", "latency_max_ms",
+                                               "mean_batch_requests", "mean_batch_keys")]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
 
 # Names and signatures of every entry point in include/pss.h.
 _c = ctypes
@@ -44,6 +69,14 @@ SIGNATURES = {
                                   _sz, _vp]),
     "pss_profile_enable": (_int, [_vp, _int]),
     "pss_profile_read": (_int, [_vp, _c.c_char_p, _sz]),
+    "pss_server_create": (_int, [_vp, _sz, _u32, _vp, _c.POINTER(_vp)]),
+    "pss_submit": (_int, [_vp, _c.POINTER(Request), _c.POINTER(_u64)]),
+    "pss_poll": (_int, [_vp, _u64, _c.POINTER(_int), _c.POINTER(_int)]),
+    "pss_wait": (_int, [_vp, _u64, _c.POINTER(_int)]),
+    "pss_cancel": (_int, [_vp, _u64]),
+    "pss_server_stats": (_int, [_vp, _c.POINTER(Stats)]),
+    "pss_server_reset_stats": (_int, [_vp]),
+    "pss_server_destroy": (None, [_vp]),
     "pss_splitters": (_int, [_vp, _int, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                              _vp]),
 }

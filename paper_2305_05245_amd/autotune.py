@@ -97,3 +97,20 @@ def tune(kt: int, vt: int, n: int, n_segs: int, lo_log2: float = 6.0, hi_log2: f
                 json.dump(cache, f, indent=1, sort_keys=True)
             os.replace(tmp, CACHE_PATH)
     return best
+
+
+if __name__ == "__main__":
+    # python -m paper_2305_05245_amd.autotune [cache.json]: tune the shapes of
+    # the 4096-array batch (int64 keys only, and u64 keys with uint32 values)
+    import sys
+
+    import workloads as W
+
+    if len(sys.argv) > 1:
+        CACHE_PATH = sys.argv[1]
+    sizes = W.segment_sizes_loguniform(4096, 6.0, 20.0, seed=12)
+    total = int(sizes.sum())
+    for kt, vt in ((3, 0), (2, 1)):
+        best = tune(kt, vt, total, sizes.size)
+        print(json.dumps({"key": kt, "val": vt, "n": total, "segs": int(sizes.size), **best}),
+              flush=True)

@@ -309,6 +309,11 @@ pss_status run_segment_sort(pss_ctx *ctx, const Plan &p, int kt, const void *key
 
 }  // namespace
 
+namespace pss {
+void set_thread_error(const char *msg) { g_thread_error = msg; }
+int ctx_device(const pss_ctx *ctx) { return ctx->device; }
+}  // namespace pss
+
 extern "C" {
 
 pss_status pss_create(int device, pss_ctx **out) {
@@ -391,6 +396,9 @@ const char *pss_status_string(pss_status s) {
     case PSS_ERR_OOM: return "PSS_ERR_OOM";
     case PSS_ERR_HIP: return "PSS_ERR_HIP";
     case PSS_ERR_WORKSPACE: return "PSS_ERR_WORKSPACE";
+    case PSS_ERR_BUDGET: return "PSS_ERR_BUDGET";
+    case PSS_ERR_BUSY: return "PSS_ERR_BUSY";
+    case PSS_ERR_CANCELLED: return "PSS_ERR_CANCELLED";
     default: return "PSS_ERR_UNKNOWN";
   }
 }

@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 
+struct pss_ctx;
+
 namespace pss {
 
 // Step 1 tile sort: one workgroup sorts kTile keys held in LDS.
@@ -100,6 +102,12 @@ constexpr uint32_t kMaxSegPasses = 4;
 
 // Synchronous read (and optional clear) of the device error word.
 hipError_t read_device_error(uint32_t *code, bool clear);
+
+// Set the calling thread's error message (pss_last_error(NULL)).
+void set_thread_error(const char *msg);
+
+// HIP device a context is bound to.
+int ctx_device(const pss_ctx *ctx);
 
 // key-type codes (same numbering as pss_key_t)
 inline int key_bytes(int kt) { return (kt == 0 || kt == 1 || kt == 4) ? 4 : 8; }

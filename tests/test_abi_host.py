@@ -114,3 +114,28 @@ def test_paper_plan(lib):
     assert p["mode"] == "paper" and p["n_blocks"] == 64 and p["n_parts"] == 64
     assert p["block_passes"] == [2]          # blocks of 16384 keys = 2 tiles
     assert p["hbm_passes"] == 3
+
+
+def test_server_entry_points_reject_null_handles(lib):
+    req = _lib.Request()
+    t = ctypes.c_uint64()
+    st = ctypes.c_int()
+    done = ctypes.c_int()
+    h = ctypes.c_void_p()
+    assert lib.pss_server_create(None, 1 << 30, 2, None, ctypes.byref(h)) == _lib.ERR_INVALID
+    assert lib.pss_submit(None, ctypes.byref(req), ctypes.byref(t)) == _lib.ERR_INVALID
+    assert lib.pss_poll(None, 1, ctypes.byref(done), ctypes.byref(st)) == _lib.ERR_INVALID
+    assert lib.pss_wait(None, 1, ctypes.byref(st)) == _lib.ERR_INVALID
+    assert lib.pss_cancel(None, 1) == _lib.ERR_INVALID
+    s = _lib.Stats()
+    assert lib.pss_server_stats(None, ctypes.byref(s)) == _lib.ERR_INVALID
+    assert lib.pss_server_reset_stats(None) == _lib.ERR_INVALID
+    lib.pss_server_destroy(None)
+    assert _lib.status_string(_lib.ERR_BUDGET) == "PSS_ERR_BUDGET"
+    assert _lib.status_string(_lib.ERR_CANCELLED) == "PSS_ERR_CANCELLED"
+
+
+def test_server_structs_match_the_header():
+    # pss_request: two enums, four pointers, two uint64; pss_stats: 7 uint64 + 7 double
+    assert ctypes.sizeof(_lib.Request) == 8 + 4 * 8 + 2 * 8
+    assert ctypes.sizeof(_lib.Stats) == 14 * 8

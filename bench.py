@@ -6,12 +6,20 @@ in HBM, into a separate output array.  Prints ONE JSON line.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--dist uniform]
                     [--log2n 28] [--all-dists] [--no-cpu-baseline]
+                    [--no-batched] [--no-serving] [--leg batched|serving]
 
 The roofline object reports the dominant kernel: its algorithmic HBM bytes per
 launch (every key read once and written once: 16 bytes per int64 key) divided
 by its mean launch time, timed with HIP events recorded by the library on the
-stream the kernel runs on, during the timed steps.  The CPU baseline is the
-sequential oracle timed on a bounded sample on the host.
+stream the kernel runs on, during the timed steps.  `traffic` is the kernel's
+measured HBM bytes per launch from the committed counter summary, while the
+kernel source still matches it.  The CPU baseline is the sequential oracle
+timed on a bounded sample on the host.
+
+Two more legs are added to the line: "batched" (4096 int64 arrays of
+log-uniform sizes sorted by one captured graph, against one sort per array)
+and "serving" (Poisson arrivals of u64 key + u32 value requests into the
+library's serving loop: p50 / p99 latency and keys/s).
 """
 from __future__ import annotations
 
@@ -40,6 +48,28 @@ def generators():
         "reverse": lambda n: W.reverse_i64(n),
         "swapped1pct": lambda n: W.swapped_i64(n, seed=6),
     }
+
+
+def measured_traffic(kernel: str, log2n: int, dist: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, scaled by a plain copy), or None when
+    the summary does not cover this kernel and workload or the kernel source
+    has changed since the counters were taken."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", "merge_2p28_int64_traffic.md")
+    src = os.path.join(ROOT, "paper_2305_05245_amd", "csrc", "pss_kernels.hip")
+    if kernel != "merge" or log2n != 28 or dist != "uniform" or not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    if not m or not h:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
+        return None
+    return int(m.group(1))
 
 
 def time_sort(pss, torch, keys_dev, out, ws, steps: int, warmup: int, profile: bool):
@@ -155,7 +185,7 @@ def bench_batched(pss, torch, steps: int, warmup: int) -> dict:
             "outputs_identical": same}
 
 
-def bench_serving(torch, capacity_hint: float, n_req: int = 20000, warm_req: int = 2000,
+def bench_serving(torch, _unused: float, n_req: int = 20000, warm_req: int = 2000,
                   budget: int = 64 << 30, streams: int = 4) -> dict:
     """Open-loop serving run: Poisson arrivals (seed 14), lognormal sizes with
     median 2^16 and sigma 1.5 clipped to [2^10, 2^24] (seed 15), half the
@@ -281,6 +311,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-array batch")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--leg", choices=("batched", "serving"),
+                    help="run only this leg and print its JSON object (for profiling)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a plain device-to-device copy of the keys (bandwidth and "
                          "counter calibration), print its line and exit")
@@ -301,6 +333,14 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     _lib.load()  # fail loudly when the HIP library is missing
+
+    if args.leg == "batched":
+        print(json.dumps(bench_batched(pss, torch, max(3, args.steps // 2), 1)), flush=True)
+        return 0
+    if args.leg == "serving":
+        print(json.dumps(bench_serving(torch, 0.0, n_req=args.serve_requests,
+                                       warm_req=max(1, args.serve_requests // 10))), flush=True)
+        return 0
 
     n = 1 << args.log2n
     gens = generators()
@@ -345,7 +385,7 @@ def main() -> int:
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(dom_name, args.log2n, args.dist),
         "bytes_per_launch": per_launch_bytes,
         "mean_launch_ms": round(per_launch_ms, 4),
     }

@@ -170,6 +170,55 @@ __device__ __forceinline__ uint32_t seg_find(const uint64_t *prefix, uint32_t n_
   return lo;
 }
 
+// LDS slot of index i: the padded layout (one spare slot after every 16, for
+// phases where each thread reads or writes 16 consecutive slots) or flat.
+template <bool PAD> __device__ __forceinline__ uint32_t lds_at(uint32_t i) {
+  return PAD ? pad16(i) : i;
+}
+
+// One chunk of a stable pairwise merge in LDS: the CI outputs from `start` on
+// of merging A = [A0, A1) and B = [A1, B1) (ties to A), into registers.  The
+// merge-path search finds how many of the first start-A0 outputs come from A;
+// then one output per step.  Outputs at or past B1 (only in a pair's last
+// chunk) are meaningless and must not be stored; computing them reads at
+// most CI slots past B1, which every LDS array using this leaves as slack.
+template <typename U, bool KV, int CI, bool PAD>
+__device__ __forceinline__ void merge_chunk(const U *sk, const uint32_t *sv, uint32_t A0,
+                                            uint32_t A1, uint32_t B1, uint32_t start,
+                                            U (&rk)[CI], uint32_t (&rv)[KV ? CI : 1]) {
+  const uint32_t la = A1 - A0, lb = B1 - A1, d = start - A0;
+  uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (sk[lds_at<PAD>(A0 + mid)] <= sk[lds_at<PAD>(A1 + d - 1 - mid)]) lo = mid + 1;
+    else hi = mid;
+  }
+  uint32_t pa = A0 + lo, pb = A1 + (d - lo);
+  U ka = sk[lds_at<PAD>(pa)], kb = sk[lds_at<PAD>(pb)];
+  uint32_t va = 0, vb = 0;
+  if constexpr (KV) {
+    va = sv[lds_at<PAD>(pa)];
+    vb = sv[lds_at<PAD>(pb)];
+  }
+#pragma unroll
+  for (int i = 0; i < CI; ++i) {
+    const bool takeA = pa < A1 && (pb >= B1 || ka <= kb);
+    rk[i] = takeA ? ka : kb;
+    if constexpr (KV) rv[i] = takeA ? va : vb;
+    const uint32_t nxt = (takeA ? pa : pb) + 1;
+    const U nk = sk[lds_at<PAD>(nxt)];
+    ka = takeA ? nk : ka;
+    kb = takeA ? kb : nk;
+    if constexpr (KV) {
+      const uint32_t nv = sv[lds_at<PAD>(nxt)];
+      va = takeA ? nv : va;
+      vb = takeA ? vb : nv;
+    }
+    pa += takeA ? 1u : 0u;
+    pb += takeA ? 0u : 1u;
+  }
+}
+
 // --------------------------------------------------------------- K1 -------
 // One workgroup sorts one tile of at most kTile keys of one segment.  Keys are
 // mapped on load (K0), each thread sorts 16 consecutive keys in registers, then
@@ -199,7 +248,8 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
     TileArgs<typename Key<KT>::U> ta) {
   using U = typename Key<KT>::U;
   constexpr uint32_t TILE = THREADS * kTileItems;
-  constexpr uint32_t P = TILE + TILE / 16 + 1;  // +1: a merge step may read one past the end
+  // padded layout of TILE slots, plus the slack a merge chunk may read
+  constexpr uint32_t P = TILE + TILE / 16 + 2 * kRoundItems + 2;
   __shared__ U sk[P];
   __shared__ uint32_t sv[KV ? P : 1];
 
@@ -236,17 +286,23 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
     sbase = seg * (ta.seg_len >> kSampleLog2) + ((j * (uint64_t)TILE) >> kSampleLog2);
   }
 
+  // All loads first (clamped into the tile, so none is conditional and all
+  // are in flight together), then the key map and the padding of a short
+  // tile with the largest key.
+  U raw[kTileItems];
+  uint32_t vraw[KV ? kTileItems : 1];
 #pragma unroll
   for (int i = 0; i < kTileItems; ++i) {
     const uint32_t idx = i * THREADS + tid;
-    U k = key_max<U>();
-    uint32_t v = 0;
-    if (idx < len) {
-      k = Key<KT>::map(in[start + idx]);
-      if constexpr (KV) v = vin[start + idx];
-    }
-    sk[pad16(idx)] = k;
-    if constexpr (KV) sv[pad16(idx)] = v;
+    const uint32_t j = idx < len ? idx : len - 1;  // len >= 1 for every tile launched
+    raw[i] = in[start + j];
+    if constexpr (KV) vraw[i] = vin[start + j];
+  }
+#pragma unroll
+  for (int i = 0; i < kTileItems; ++i) {
+    const uint32_t idx = i * THREADS + tid;
+    sk[pad16(idx)] = idx < len ? Key<KT>::map(raw[i]) : key_max<U>();
+    if constexpr (KV) sv[pad16(idx)] = idx < len ? vraw[i] : 0u;
   }
   __syncthreads();
 
@@ -259,53 +315,6 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
     if constexpr (KV) rv[i] = sv[pad16(idx)];
   }
   register_sort<U, KV, kTileItems>(rk, rv);
-
-  for (uint32_t L = kTileItems; L < TILE; L *= 2) {
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kTileItems; ++i) {
-      const uint32_t idx = tid * kTileItems + i;
-      sk[pad16(idx)] = rk[i];
-      if constexpr (KV) sv[pad16(idx)] = rv[i];
-    }
-    __syncthreads();
-    // merge path: how many of this thread's first output position's
-    // predecessors come from the left run A (ties go to A: stable)
-    const uint32_t pos = tid * kTileItems;
-    const uint32_t diag = pos & (2 * L - 1);
-    const uint32_t a0 = pos - diag, b0 = a0 + L;
-    uint32_t lo = diag > L ? diag - L : 0, hi = diag < L ? diag : L;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (sk[pad16(a0 + mid)] <= sk[pad16(b0 + diag - 1 - mid)]) lo = mid + 1;
-      else hi = mid;
-    }
-    uint32_t ai = lo, bi = diag - lo;
-    U ka = sk[pad16(a0 + (ai < L ? ai : L - 1))];
-    U kb = sk[pad16(b0 + (bi < L ? bi : L - 1))];
-    uint32_t va = 0, vb = 0;
-    if constexpr (KV) {
-      va = sv[pad16(a0 + (ai < L ? ai : L - 1))];
-      vb = sv[pad16(b0 + (bi < L ? bi : L - 1))];
-    }
-#pragma unroll
-    for (int i = 0; i < kTileItems; ++i) {
-      const bool takeA = ai < L && (bi >= L || ka <= kb);
-      rk[i] = takeA ? ka : kb;
-      if constexpr (KV) rv[i] = takeA ? va : vb;
-      const uint32_t nxt = takeA ? a0 + ai + 1 : b0 + bi + 1;
-      const U nk = sk[pad16(nxt)];
-      ka = takeA ? nk : ka;
-      kb = takeA ? kb : nk;
-      if constexpr (KV) {
-        const uint32_t nv = sv[pad16(nxt)];
-        va = takeA ? nv : va;
-        vb = takeA ? vb : nv;
-      }
-      ai += takeA ? 1u : 0u;
-      bi += takeA ? 0u : 1u;
-    }
-  }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kTileItems; ++i) {
@@ -314,20 +323,52 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
     if constexpr (KV) sv[pad16(idx)] = rv[i];
   }
   __syncthreads();
+
+  // Rounds of pairwise merges of runs of L keys.  Each pair's output is cut
+  // into chunks of CI keys (never crossing into the next pair), one chunk per
+  // thread: at most THREADS chunks per round.  The first round reads the
+  // padded layout; every round writes the flat one (CI is odd, so the
+  // threads' chunk stores do not collide in LDS banks).
+  constexpr int CI = kRoundItems;
+  U mk[CI];
+  uint32_t mv[KV ? CI : 1];
+  for (uint32_t L = kTileItems; L < TILE; L *= 2) {
+    const uint32_t cpp = (2 * L + CI - 1) / CI;  // chunks per pair
+    const uint32_t q = tid / cpp, c = tid - q * cpp;
+    const uint32_t A0 = q * 2 * L;
+    const bool active = A0 < TILE;
+    const uint32_t cs = A0 + c * CI;  // this thread's first output
+    const uint32_t count = active ? (A0 + 2 * L - cs < (uint32_t)CI ? A0 + 2 * L - cs : CI) : 0;
+    if (active) {
+      if (L == kTileItems)
+        merge_chunk<U, KV, CI, true>(sk, sv, A0, A0 + L, A0 + 2 * L, cs, mk, mv);
+      else
+        merge_chunk<U, KV, CI, false>(sk, sv, A0, A0 + L, A0 + 2 * L, cs, mk, mv);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < CI; ++i) {
+      if ((uint32_t)i < count) {
+        sk[cs + i] = mk[i];
+        if constexpr (KV) sv[cs + i] = mv[i];
+      }
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int i = 0; i < kTileItems; ++i) {
     const uint32_t idx = i * THREADS + tid;
     if (idx < len) {
-      const U k = sk[pad16(idx)];
+      const U k = sk[idx];
       out[start + idx] = final_pass ? Key<KT>::unmap(k) : k;
-      if constexpr (KV) vout[start + idx] = sv[pad16(idx)];
+      if constexpr (KV) vout[start + idx] = sv[idx];
     }
   }
   // regular samples of the sorted tile (every kSample-th key, tile positions
   // kSample*i + kSample-1) for the next level's splitter search
   if (samples != nullptr) {
     for (uint32_t i = tid; i < (len >> kSampleLog2); i += THREADS)
-      samples[sbase + i] = sk[pad16((i << kSampleLog2) + kSample - 1)];
+      samples[sbase + i] = sk[(i << kSampleLog2) + kSample - 1];
   }
 }
 
@@ -995,50 +1036,6 @@ __device__ __forceinline__ PartInfo part_info(const RunGeom &g, uint64_t pidx,
   return pi;
 }
 
-// One chunk of a stable pairwise merge in LDS: the outputs [start, start+count)
-// of merging A = [A0, A1) and B = [A1, B1) (ties to A), into registers.  The
-// merge-path search finds how many of the first start-A0 outputs come from A;
-// then one output per step.  Reads one slot past B1 at most (LDS has slack).
-template <typename U, bool KV, int ITEMS>
-__device__ __forceinline__ void merge_chunk(const U *sk, const uint32_t *sv, uint32_t A0,
-                                            uint32_t A1, uint32_t B1, uint32_t start,
-                                            uint32_t count, U (&rk)[ITEMS],
-                                            uint32_t (&rv)[KV ? ITEMS : 1]) {
-  const uint32_t la = A1 - A0, lb = B1 - A1, d = start - A0;
-  uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (sk[pad16(A0 + mid)] <= sk[pad16(A1 + d - 1 - mid)]) lo = mid + 1;
-    else hi = mid;
-  }
-  uint32_t pa = A0 + lo, pb = A1 + (d - lo);
-  U ka = sk[pad16(pa)], kb = sk[pad16(pb)];
-  uint32_t va = 0, vb = 0;
-  if constexpr (KV) {
-    va = sv[pad16(pa)];
-    vb = sv[pad16(pb)];
-  }
-#pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    if ((uint32_t)i < count) {
-      const bool takeA = pa < A1 && (pb >= B1 || ka <= kb);
-      rk[i] = takeA ? ka : kb;
-      if constexpr (KV) rv[i] = takeA ? va : vb;
-      const uint32_t nxt = (takeA ? pa : pb) + 1;
-      const U nk = sk[pad16(nxt)];
-      ka = takeA ? nk : ka;
-      kb = takeA ? kb : nk;
-      if constexpr (KV) {
-        const uint32_t nv = sv[pad16(nxt)];
-        va = takeA ? nv : va;
-        vb = takeA ? vb : nv;
-      }
-      pa += takeA ? 1u : 0u;
-      pb += takeA ? 0u : 1u;
-    }
-  }
-}
-
 // Largest b in [0, F) with soff[b] <= pos (requires pos < soff[F]).
 __device__ __forceinline__ uint32_t find_segment(const uint32_t *soff, uint32_t F, uint32_t pos) {
   uint32_t lo = 0, hi = F;
@@ -1072,12 +1069,13 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
     typename Key<KT>::U *__restrict__ samples, uint32_t *__restrict__ prefix) {
   using U = typename Key<KT>::U;
   constexpr bool KV = VMODE != 0;
-  constexpr uint32_t P = kPart + kPart / 16 + 1;  // +1: a merge step may read one past the end
+  constexpr uint32_t P = kPart + 2 * kRoundItems + 2;  // flat layout plus merge-chunk slack
   __shared__ U sk[P];
   __shared__ uint32_t sv[KV ? P : 1];
   __shared__ uint32_t soff[MAXF + 1];
   __shared__ uint32_t cpre[MAXF <= 64 ? 64 / 2 + 2 : 1];
   __shared__ uint64_t ssrc[MAXF];
+  __shared__ uint32_t sseg[MAXF <= 64 ? kPart / 4 : 1];  // segment of each position, bytes
   __shared__ uint32_t wsum[kMergeThreads / 64 + 1];
   __shared__ uint32_t hist[VMODE == 2 ? (kPart / kChunk) * kMaxSampledFan : 1];
 
@@ -1126,16 +1124,52 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
   {
     uint64_t addr[kMergeItems];
     uint32_t runid[VMODE == 2 ? kMergeItems : 1];
-    uint32_t b = tid < M ? find_segment(soff, F, tid) : 0;
+    if constexpr (MAXF <= 64) {
+      // Label every position with its segment (one byte each): thread t
+      // labels positions 16t..16t+15, so each item below finds its segment
+      // with one independent LDS read instead of a walk over the offsets.
+      const uint32_t p0 = tid * 16;
+      if (p0 < M) {
+        uint32_t b = find_segment(soff, F, p0);
+        uint32_t nxt = soff[b + 1];
+        uint32_t wd[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int i = 0; i < kMergeItems; ++i) {
-      const uint32_t idx = i * kMergeThreads + tid;
-      addr[i] = 0;
-      if (idx < M) {
-        while (soff[b + 1] <= idx) ++b;
-        addr[i] = ssrc[b] + (idx - soff[b]);
+        for (int j = 0; j < 16; ++j) {
+          if (p0 + j < M) {
+            while (p0 + j >= nxt) nxt = soff[++b + 1];
+          }
+          wd[j >> 2] |= b << (8 * (j & 3));
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sseg[tid * 4 + j] = wd[j];
       }
-      if constexpr (VMODE == 2) runid[i] = b;
+      for (uint32_t b = tid; b < F; b += kMergeThreads) ssrc[b] -= soff[b];
+      __syncthreads();
+      const uint8_t *seg_of = reinterpret_cast<const uint8_t *>(sseg);
+      uint32_t bi[kMergeItems];
+#pragma unroll
+      for (int i = 0; i < kMergeItems; ++i) {
+        const uint32_t idx = i * kMergeThreads + tid;
+        bi[i] = idx < M ? seg_of[idx] : 0u;
+      }
+#pragma unroll
+      for (int i = 0; i < kMergeItems; ++i) {
+        const uint32_t idx = i * kMergeThreads + tid;
+        addr[i] = ssrc[bi[i]] + idx;
+        if constexpr (VMODE == 2) runid[i] = bi[i];
+      }
+    } else {
+      uint32_t b = tid < M ? find_segment(soff, F, tid) : 0;
+#pragma unroll
+      for (int i = 0; i < kMergeItems; ++i) {
+        const uint32_t idx = i * kMergeThreads + tid;
+        addr[i] = 0;
+        if (idx < M) {
+          while (soff[b + 1] <= idx) ++b;
+          addr[i] = ssrc[b] + (idx - soff[b]);
+        }
+        if constexpr (VMODE == 2) runid[i] = b;
+      }
     }
     U kreg[kMergeItems];
     uint32_t vreg[KV ? kMergeItems : 1];
@@ -1150,8 +1184,8 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
     for (int i = 0; i < kMergeItems; ++i) {
       const uint32_t idx = i * kMergeThreads + tid;
       if (idx < M) {
-        sk[pad16(idx)] = kreg[i];
-        if constexpr (KV) sv[pad16(idx)] = vreg[i];
+        sk[idx] = kreg[i];
+        if constexpr (KV) sv[idx] = vreg[i];
       }
     }
   }
@@ -1191,14 +1225,14 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
         const uint32_t B1 = soff[s0 + 2 * w < F ? s0 + 2 * w : F];
         start = A0 + (tid - cpre[lo]) * CI;
         count = B1 - start < (uint32_t)CI ? B1 - start : (uint32_t)CI;
-        merge_chunk<U, KV, CI>(sk, sv, A0, A1, B1, start, count, rk, rv);
+        merge_chunk<U, KV, CI, false>(sk, sv, A0, A1, B1, start, rk, rv);
       }
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < CI; ++i) {
         if ((uint32_t)i < count) {
-          sk[pad16(start + i)] = rk[i];
-          if constexpr (KV) sv[pad16(start + i)] = rv[i];
+          sk[start + i] = rk[i];
+          if constexpr (KV) sv[start + i] = rv[i];
         }
       }
       __syncthreads();
@@ -1224,7 +1258,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
         uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
         while (lo < hi) {
           const uint32_t mid = (lo + hi) >> 1;
-          if (sk[pad16(A0 + mid)] <= sk[pad16(A1 + d - 1 - mid)]) lo = mid + 1;
+          if (sk[A0 + mid] <= sk[A1 + d - 1 - mid]) lo = mid + 1;
           else hi = mid;
         }
         ai = lo;
@@ -1233,11 +1267,11 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
         uint32_t ib = A1 + (bi < lb ? bi : (lb ? lb - 1 : 0));
         ia = ia < M ? ia : M - 1;
         ib = ib < M ? ib : M - 1;
-        ka = sk[pad16(ia)];
-        kb = sk[pad16(ib)];
+        ka = sk[ia];
+        kb = sk[ib];
         if constexpr (KV) {
-          va = sv[pad16(ia)];
-          vb = sv[pad16(ib)];
+          va = sv[ia];
+          vb = sv[ib];
         }
       };
       locate(p0);
@@ -1250,11 +1284,11 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
           if constexpr (KV) rv[i] = takeA ? va : vb;
           uint32_t nxt = takeA ? A0 + ai + 1 : A1 + bi + 1;
           nxt = nxt < M ? nxt : M - 1;
-          const U nk = sk[pad16(nxt)];
+          const U nk = sk[nxt];
           ka = takeA ? nk : ka;
           kb = takeA ? kb : nk;
           if constexpr (KV) {
-            const uint32_t nv = sv[pad16(nxt)];
+            const uint32_t nv = sv[nxt];
             va = takeA ? nv : va;
             vb = takeA ? vb : nv;
           }
@@ -1268,8 +1302,8 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
 #pragma unroll
       for (int i = 0; i < kMergeItems; ++i) {
         if (p0 + i < M) {
-          sk[pad16(p0 + i)] = rk[i];
-          if constexpr (KV) sv[pad16(p0 + i)] = rv[i];
+          sk[p0 + i] = rk[i];
+          if constexpr (KV) sv[p0 + i] = rv[i];
         }
       }
     }
@@ -1281,9 +1315,9 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
   for (int i = 0; i < kMergeItems; ++i) {
     const uint32_t idx = i * kMergeThreads + tid;
     if (idx < M) {
-      const U k = sk[pad16(idx)];
+      const U k = sk[idx];
       dst[pi.out_off + idx] = final_pass ? Key<KT>::unmap(k) : k;
-      if constexpr (KV) vdst[pi.out_off + idx] = sv[pad16(idx)];
+      if constexpr (KV) vdst[pi.out_off + idx] = sv[idx];
     }
   }
   if (write_samples && !g.paper) {
@@ -1298,7 +1332,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
       sbase = seg * (g.seg_len >> kSampleLog2) + ((gg * g.group_len + rlo) >> kSampleLog2);
     }
     for (uint32_t i = tid; i < (M >> kSampleLog2); i += kMergeThreads)
-      samples[sbase + i] = sk[pad16((i << kSampleLog2) + kSample - 1)];
+      samples[sbase + i] = sk[(i << kSampleLog2) + kSample - 1];
   }
   if constexpr (VMODE == 2) {
     // per-run prefix counts at every kChunk-th output of this partition
@@ -1306,7 +1340,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
     for (uint32_t i = tid; i < nch * F; i += kMergeThreads) hist[i] = 0;
     __syncthreads();
     for (uint32_t i = tid; i < M; i += kMergeThreads)
-      atomicAdd(&hist[(i / kChunk) * F + sv[pad16(i)]], 1u);
+      atomicAdd(&hist[(i / kChunk) * F + sv[i]], 1u);
     __syncthreads();
     const uint64_t prow0 = (uint64_t)blockIdx.x * (kPart / kChunk);
     for (uint32_t b = tid; b < F; b += kMergeThreads) {

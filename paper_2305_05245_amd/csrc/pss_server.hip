@@ -66,30 +66,25 @@ __global__ __launch_bounds__(kCopyThreads) void batch_copy_kernel(CopyTables t, 
   const uint64_t base = t.seg_off[s] + first;
   T *req_k = reinterpret_cast<T *>(t.kptr[s]) + first;
   T *bat_k = batch_keys + base;
+  uint32_t *req_v = KV ? reinterpret_cast<uint32_t *>(t.vptr[s]) + first : nullptr;
+  uint32_t *bat_v = KV ? batch_vals + base : nullptr;
+  // every load of the chunk first (all in flight together), then the stores
   T tk[kCopyItems];
+  uint32_t tv[KV ? kCopyItems : 1];
 #pragma unroll
   for (uint32_t u = 0; u < kCopyItems; ++u) {
     const uint64_t i = (uint64_t)u * kCopyThreads + threadIdx.x;
-    if (i < len) tk[u] = GATHER ? req_k[i] : bat_k[i];
-  }
-#pragma unroll
-  for (uint32_t u = 0; u < kCopyItems; ++u) {
-    const uint64_t i = (uint64_t)u * kCopyThreads + threadIdx.x;
-    if (i < len) (GATHER ? bat_k : req_k)[i] = tk[u];
-  }
-  if constexpr (KV) {
-    uint32_t *req_v = reinterpret_cast<uint32_t *>(t.vptr[s]) + first;
-    uint32_t *bat_v = batch_vals + base;
-    uint32_t tv[kCopyItems];
-#pragma unroll
-    for (uint32_t u = 0; u < kCopyItems; ++u) {
-      const uint64_t i = (uint64_t)u * kCopyThreads + threadIdx.x;
-      if (i < len) tv[u] = GATHER ? req_v[i] : bat_v[i];
+    if (i < len) {
+      tk[u] = GATHER ? req_k[i] : bat_k[i];
+      if constexpr (KV) tv[u] = GATHER ? req_v[i] : bat_v[i];
     }
+  }
 #pragma unroll
-    for (uint32_t u = 0; u < kCopyItems; ++u) {
-      const uint64_t i = (uint64_t)u * kCopyThreads + threadIdx.x;
-      if (i < len) (GATHER ? bat_v : req_v)[i] = tv[u];
+  for (uint32_t u = 0; u < kCopyItems; ++u) {
+    const uint64_t i = (uint64_t)u * kCopyThreads + threadIdx.x;
+    if (i < len) {
+      (GATHER ? bat_k : req_k)[i] = tk[u];
+      if constexpr (KV) (GATHER ? bat_v : req_v)[i] = tv[u];
     }
   }
 }

@@ -23,6 +23,9 @@ constexpr int kPart = kMergeThreads * kMergeItems;  // 8192 keys
 // per round, ceil-rounded chunks of 17 keys still fit in kMergeThreads
 // ((8192 + 32 * 16) / 17 <= 512).
 constexpr int kRoundItems = 17;
+// Keys-only merges keep this many slots of the largest key after every run in
+// LDS (at least kRoundItems), so their merge steps need no bound checks.
+constexpr uint32_t kGap = kRoundItems + 1;
 
 // Step 2 splitter search: one 64-lane workgroup per splitter.
 constexpr int kCorankThreads = 64;

@@ -219,6 +219,47 @@ __device__ __forceinline__ void merge_chunk(const U *sk, const uint32_t *sv, uin
   }
 }
 
+// Keys-only chunk merge of two runs that are each followed in LDS by at least
+// CI copies of the largest key: A = sk[a0, a0 + la), B = sk[b0, b0 + lb).  It
+// produces outputs d .. d+CI-1 of their merged order.  After the merge-path
+// search, every step outputs the smaller of the two heads and replaces it with
+// the next key of its run.  Equal keys are bit-identical, so which run
+// supplies a tie does not change the output; a used-up run shows the largest
+// key from its gap, so no bound checks are needed, and a chunk reads at most
+// CI slots past the end of a run.
+template <typename U, int CI>
+__device__ __forceinline__ void merge_chunk_keys(const U *sk, uint32_t a0, uint32_t la,
+                                                 uint32_t b0, uint32_t lb, uint32_t d,
+                                                 U (&rk)[CI]) {
+  uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (sk[a0 + mid] <= sk[b0 + d - 1 - mid]) lo = mid + 1;
+    else hi = mid;
+  }
+  // positions as LDS byte offsets, so a step needs no index arithmetic
+  const uint32_t pa = (a0 + lo) * (uint32_t)sizeof(U), pb = (b0 + (d - lo)) * (uint32_t)sizeof(U);
+  const char *base = reinterpret_cast<const char *>(sk);
+  const U ka = *reinterpret_cast<const U *>(base + pa);
+  const U kb = *reinterpret_cast<const U *>(base + pb);
+  const bool af = ka <= kb;
+  U x = af ? ka : kb, y = af ? kb : ka;  // x: the next output, y: the other head
+  uint32_t px = af ? pa : pb, py = af ? pb : pa;
+#pragma unroll
+  for (int i = 0; i < CI; ++i) {
+    rk[i] = x;
+    const uint32_t pn = px + (uint32_t)sizeof(U);
+    const U nk = *reinterpret_cast<const U *>(base + pn);
+    const bool keep = nk <= y;
+    const U nx = keep ? nk : y, ny = keep ? y : nk;
+    const uint32_t npx = keep ? pn : py, npy = keep ? py : pn;
+    x = nx;
+    y = ny;
+    px = npx;
+    py = npy;
+  }
+}
+
 // --------------------------------------------------------------- K1 -------
 // One workgroup sorts one tile of at most kTile keys of one segment.  Keys are
 // mapped on load (K0), each thread sorts 16 consecutive keys in registers, then
@@ -1069,7 +1110,12 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
     typename Key<KT>::U *__restrict__ samples, uint32_t *__restrict__ prefix) {
   using U = typename Key<KT>::U;
   constexpr bool KV = VMODE != 0;
-  constexpr uint32_t P = kPart + 2 * kRoundItems + 2;  // flat layout plus merge-chunk slack
+  // Keys-only merges of at most 32 runs leave kGap slots holding the largest
+  // key after every segment in LDS (see merge_chunk_keys); others use the
+  // flat layout.  Both add the slack a merge chunk may read past the end.
+  constexpr bool GAPS = VMODE == 0 && MAXF <= 32;
+  constexpr uint32_t G = GAPS ? kGap : 0;
+  constexpr uint32_t P = kPart + MAXF * G + 2 * kRoundItems + 2;
   __shared__ U sk[P];
   __shared__ uint32_t sv[KV ? P : 1];
   __shared__ uint32_t soff[MAXF + 1];
@@ -1124,6 +1170,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
   {
     uint64_t addr[kMergeItems];
     uint32_t runid[VMODE == 2 ? kMergeItems : 1];
+    uint32_t lpos[kMergeItems];  // LDS slot of each item
     if constexpr (MAXF <= 64) {
       // Label every position with its segment (one byte each): thread t
       // labels positions 16t..16t+15, so each item below finds its segment
@@ -1156,6 +1203,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
       for (int i = 0; i < kMergeItems; ++i) {
         const uint32_t idx = i * kMergeThreads + tid;
         addr[i] = ssrc[bi[i]] + idx;
+        lpos[i] = idx + bi[i] * G;
         if constexpr (VMODE == 2) runid[i] = bi[i];
       }
     } else {
@@ -1168,6 +1216,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
           while (soff[b + 1] <= idx) ++b;
           addr[i] = ssrc[b] + (idx - soff[b]);
         }
+        lpos[i] = idx;
         if constexpr (VMODE == 2) runid[i] = b;
       }
     }
@@ -1184,8 +1233,15 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
     for (int i = 0; i < kMergeItems; ++i) {
       const uint32_t idx = i * kMergeThreads + tid;
       if (idx < M) {
-        sk[idx] = kreg[i];
-        if constexpr (KV) sv[idx] = vreg[i];
+        sk[lpos[i]] = kreg[i];
+        if constexpr (KV) sv[lpos[i]] = vreg[i];
+      }
+    }
+    if constexpr (GAPS) {
+      // the gap after segment b: slots soff[b+1] + b*G .. + G
+      for (uint32_t t = tid; t < F * G; t += kMergeThreads) {
+        const uint32_t b = t / G;
+        sk[soff[b + 1] + b * G + (t - b * G)] = key_max<U>();
       }
     }
   }
@@ -1211,8 +1267,28 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
       if (nchunks > kMergeThreads && tid == 0) report(kErrPartSize);  // cannot happen for M <= kPart
       U rk[CI];
       uint32_t rv[KV ? CI : 1];
-      uint32_t start = 0, count = 0;
-      if (tid < nchunks) {
+      uint32_t start = 0, count = 0, gap_at = 0;
+      bool last = false;
+      if (GAPS && tid < nchunks) {
+        uint32_t lo = 0, hi = npairs;  // pair q with cpre[q] <= tid < cpre[q+1]
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (cpre[mid] <= tid) lo = mid;
+          else hi = mid;
+        }
+        const uint32_t sa = 2 * w * lo;
+        const uint32_t sb = sa + w < F ? sa + w : F;
+        const uint32_t se = sa + 2 * w < F ? sa + 2 * w : F;
+        const uint32_t la = soff[sb] - soff[sa], lb = soff[se] - soff[sb];
+        const uint32_t a0 = soff[sa] + sa * G;
+        const uint32_t b0 = sb < F ? soff[sb] + sb * G : a0 + la;  // no B: read A's gap
+        const uint32_t o = (tid - cpre[lo]) * CI;
+        count = la + lb - o < (uint32_t)CI ? la + lb - o : (uint32_t)CI;
+        start = a0 + o;
+        last = o + count == la + lb;
+        gap_at = a0 + la + lb;
+        merge_chunk_keys<U, CI>(sk, a0, la, b0, lb, o, rk);
+      } else if (!GAPS && tid < nchunks) {
         uint32_t lo = 0, hi = npairs;  // pair q with cpre[q] <= tid < cpre[q+1]
         while (hi - lo > 1) {
           const uint32_t mid = (lo + hi) >> 1;
@@ -1234,6 +1310,10 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
           sk[start + i] = rk[i];
           if constexpr (KV) sv[start + i] = rv[i];
         }
+      }
+      if (GAPS && last) {
+        // the merged run's gap (the pair's region has room for it)
+        for (uint32_t j = 0; j < G; ++j) sk[gap_at + j] = key_max<U>();
       }
       __syncthreads();
     }
@@ -1754,6 +1834,8 @@ hipError_t launch_merge(int kt, int vmode, const void *src, const uint32_t *vsrc
       return hipGetLastError();
     };
     const bool kv = vmode == 1;
+    if (!kv && g.fan <= 32)
+      return go(std::integral_constant<int, 0>{}, std::integral_constant<uint32_t, 32>{});
     if (g.fan <= 64)
       return kv ? go(std::integral_constant<int, 1>{}, std::integral_constant<uint32_t, 64>{})
                 : go(std::integral_constant<int, 0>{}, std::integral_constant<uint32_t, 64>{});

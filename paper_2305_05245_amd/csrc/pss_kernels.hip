@@ -93,6 +93,14 @@ template <typename U> __device__ __forceinline__ constexpr U key_max() { return 
 // writing its 16 consecutive keys does not hit the same bank as its neighbours.
 __device__ __forceinline__ uint32_t pad16(uint32_t i) { return i + (i >> 4); }
 
+// Order LDS accesses within one wave: everything this wave wrote before is
+// visible to everything it reads after (no other wave takes part).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ----------------------------------------------------- sorting networks ----
 // Index pairs of Batcher's odd-even merge sort on N registers (unstable,
 // keys only) and of odd-even transposition sort (stable: only neighbours are
@@ -356,28 +364,34 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
     if constexpr (KV) rv[i] = sv[pad16(idx)];
   }
   register_sort<U, KV, kTileItems>(rk, rv);
-  __syncthreads();
+  // every wave writes back the keys it read (its own 1024 positions)
+  wave_sync();
 #pragma unroll
   for (int i = 0; i < kTileItems; ++i) {
     const uint32_t idx = tid * kTileItems + i;
     sk[pad16(idx)] = rk[i];
     if constexpr (KV) sv[pad16(idx)] = rv[i];
   }
-  __syncthreads();
+  wave_sync();
 
   // Rounds of pairwise merges of runs of L keys.  Each pair's output is cut
   // into chunks of CI keys (never crossing into the next pair), one chunk per
   // thread: at most THREADS chunks per round.  The first round reads the
   // padded layout; every round writes the flat one (CI is odd, so the
-  // threads' chunk stores do not collide in LDS banks).
+  // threads' chunk stores do not collide in LDS banks).  While a pair fits in
+  // the 1024 keys that one wave's threads sorted, each wave merges only its
+  // own keys and, after the first round, synchronises only with itself.
   constexpr int CI = kRoundItems;
+  constexpr uint32_t WKEYS = 64 * kTileItems;  // keys per wave
   U mk[CI];
   uint32_t mv[KV ? CI : 1];
-  for (uint32_t L = kTileItems; L < TILE; L *= 2) {
+  const uint32_t lane = tid & 63, wbase = (tid >> 6) * WKEYS;
+  uint32_t L = kTileItems;
+  for (; L < TILE && 2 * L <= WKEYS; L *= 2) {
     const uint32_t cpp = (2 * L + CI - 1) / CI;  // chunks per pair
-    const uint32_t q = tid / cpp, c = tid - q * cpp;
-    const uint32_t A0 = q * 2 * L;
-    const bool active = A0 < TILE;
+    const uint32_t q = lane / cpp, c = lane - q * cpp;
+    const bool active = q < WKEYS / (2 * L);
+    const uint32_t A0 = wbase + q * 2 * L;
     const uint32_t cs = A0 + c * CI;  // this thread's first output
     const uint32_t count = active ? (A0 + 2 * L - cs < (uint32_t)CI ? A0 + 2 * L - cs : CI) : 0;
     if (active) {
@@ -386,6 +400,30 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
       else
         merge_chunk<U, KV, CI, false>(sk, sv, A0, A0 + L, A0 + 2 * L, cs, mk, mv);
     }
+    // The first round moves every wave's keys from the padded layout to the
+    // flat one, whose slots overlap the previous wave's padded ones: all
+    // waves must finish reading first.  Later rounds stay in the wave's own
+    // flat slots.
+    if (L == kTileItems) __syncthreads();
+    else wave_sync();
+#pragma unroll
+    for (int i = 0; i < CI; ++i) {
+      if ((uint32_t)i < count) {
+        sk[cs + i] = mk[i];
+        if constexpr (KV) sv[cs + i] = mv[i];
+      }
+    }
+    wave_sync();
+  }
+  __syncthreads();
+  for (; L < TILE; L *= 2) {
+    const uint32_t cpp = (2 * L + CI - 1) / CI;  // chunks per pair
+    const uint32_t q = tid / cpp, c = tid - q * cpp;
+    const uint32_t A0 = q * 2 * L;
+    const bool active = A0 < TILE;
+    const uint32_t cs = A0 + c * CI;  // this thread's first output
+    const uint32_t count = active ? (A0 + 2 * L - cs < (uint32_t)CI ? A0 + 2 * L - cs : CI) : 0;
+    if (active) merge_chunk<U, KV, CI, false>(sk, sv, A0, A0 + L, A0 + 2 * L, cs, mk, mv);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < CI; ++i) {
@@ -1119,7 +1157,8 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
   __shared__ U sk[P];
   __shared__ uint32_t sv[KV ? P : 1];
   __shared__ uint32_t soff[MAXF + 1];
-  __shared__ uint32_t cpre[MAXF <= 64 ? 64 / 2 + 2 : 1];
+  // chunk prefixes over pairs, for each merge round (fan <= 64: 6 rounds)
+  __shared__ uint32_t cpre[MAXF <= 64 ? 6 * 33 : 1];
   __shared__ uint64_t ssrc[MAXF];
   __shared__ uint32_t sseg[MAXF <= 64 ? kPart / 4 : 1];  // segment of each position, bytes
   __shared__ uint32_t wsum[kMergeThreads / 64 + 1];
@@ -1149,16 +1188,63 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
     write_samples = write_samples && !final_pass;
   }
 
-  for (uint32_t b = tid; b < F; b += kMergeThreads) {
-    const uint32_t lo = pi.lo_row[b], hi = pi.hi_row[b];
-    const uint32_t len = run_length(pi.group_len, R, b);
-    const bool ok = lo <= hi && hi <= len;
-    if (!ok) report(kErrSplitRow);
-    soff[b] = ok ? hi - lo : (uint32_t)kPart + 1;  // forces the size check below to fail
-    ssrc[b] = pi.group_start + (uint64_t)b * R + lo;
+  if constexpr (MAXF <= 64) {
+    // one wave: segment sizes, their exclusive scan, and the chunk prefix
+    // of every merge round (from registers, so no other wave waits on it)
+    if (tid < 64) {
+      uint32_t c = 0;
+      if (tid < F) {
+        const uint32_t lo = pi.lo_row[tid], hi = pi.hi_row[tid];
+        const uint32_t len = run_length(pi.group_len, R, tid);
+        const bool ok = lo <= hi && hi <= len;
+        if (!ok) report(kErrSplitRow);
+        c = ok ? hi - lo : (uint32_t)kPart + 1;  // forces the size check below to fail
+        ssrc[tid] = pi.group_start + (uint64_t)tid * R + lo;
+      }
+      uint32_t x = c;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if ((int)tid >= d) x += y;
+      }
+      const uint32_t e = x - c;  // soff[tid]; lanes at or past F hold the total
+      const uint32_t total = __shfl(x, 63, 64);
+      if (tid < F) soff[tid] = e;
+      if (tid == 0) soff[F] = total;
+      auto off_at = [&](uint32_t j) {  // soff[j] for j <= F (all lanes take part)
+        const uint32_t v = __shfl(e, (int)(j < 64 ? j : 63), 64);
+        return j < 64 ? v : total;
+      };
+      uint32_t r = 0;
+      for (uint32_t w = 1; w < F; w <<= 1, ++r) {
+        const uint32_t np = (F + 2 * w - 1) / (2 * w);
+        const uint32_t j0 = 2 * w * tid < F ? 2 * w * tid : F;
+        const uint32_t j1 = 2 * w * tid + 2 * w < F ? 2 * w * tid + 2 * w : F;
+        const uint32_t a0 = off_at(j0), b1 = off_at(j1);
+        const uint32_t cc = tid < np ? (b1 - a0 + kRoundItems - 1) / kRoundItems : 0u;
+        uint32_t xc = cc;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t y = __shfl_up(xc, d, 64);
+          if ((int)tid >= d) xc += y;
+        }
+        if (tid < np) cpre[r * 33 + tid] = xc - cc;
+        if (tid == np - 1) cpre[r * 33 + np] = xc;
+      }
+    }
+    __syncthreads();
+  } else {
+    for (uint32_t b = tid; b < F; b += kMergeThreads) {
+      const uint32_t lo = pi.lo_row[b], hi = pi.hi_row[b];
+      const uint32_t len = run_length(pi.group_len, R, b);
+      const bool ok = lo <= hi && hi <= len;
+      if (!ok) report(kErrSplitRow);
+      soff[b] = ok ? hi - lo : (uint32_t)kPart + 1;  // forces the size check below to fail
+      ssrc[b] = pi.group_start + (uint64_t)b * R + lo;
+    }
+    __syncthreads();
+    block_exclusive_scan(soff, F, wsum);
   }
-  __syncthreads();
-  block_exclusive_scan(soff, F, wsum);
   const uint32_t M = soff[F];
   if (M != pi.size) {  // split rows inconsistent with the partition: stop
     if (tid == 0) report(kErrPartSize);
@@ -1254,26 +1340,21 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
     // into the next pair; a chunk prefix over pairs maps threads to chunks.
     // With at most 32 pairs, M <= kPart keys fit in kMergeThreads chunks.
     constexpr int CI = kRoundItems;
-    for (uint32_t w = 1; w < F; w <<= 1) {
+    uint32_t round = 0;
+    for (uint32_t w = 1; w < F; w <<= 1, ++round) {
       const uint32_t npairs = (F + 2 * w - 1) / (2 * w);
-      for (uint32_t q = tid; q < npairs; q += kMergeThreads) {
-        const uint32_t a0 = soff[2 * w * q];
-        const uint32_t b1 = soff[2 * w * q + 2 * w < F ? 2 * w * q + 2 * w : F];
-        cpre[q] = (b1 - a0 + CI - 1) / CI;
-      }
-      __syncthreads();
-      block_exclusive_scan(cpre, npairs, wsum);
-      const uint32_t nchunks = cpre[npairs];
+      const uint32_t *cp = cpre + round * 33;
+      const uint32_t nchunks = cp[npairs];
       if (nchunks > kMergeThreads && tid == 0) report(kErrPartSize);  // cannot happen for M <= kPart
       U rk[CI];
       uint32_t rv[KV ? CI : 1];
       uint32_t start = 0, count = 0, gap_at = 0;
       bool last = false;
       if (GAPS && tid < nchunks) {
-        uint32_t lo = 0, hi = npairs;  // pair q with cpre[q] <= tid < cpre[q+1]
+        uint32_t lo = 0, hi = npairs;  // pair q with cp[q] <= tid < cp[q+1]
         while (hi - lo > 1) {
           const uint32_t mid = (lo + hi) >> 1;
-          if (cpre[mid] <= tid) lo = mid;
+          if (cp[mid] <= tid) lo = mid;
           else hi = mid;
         }
         const uint32_t sa = 2 * w * lo;
@@ -1282,24 +1363,24 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
         const uint32_t la = soff[sb] - soff[sa], lb = soff[se] - soff[sb];
         const uint32_t a0 = soff[sa] + sa * G;
         const uint32_t b0 = sb < F ? soff[sb] + sb * G : a0 + la;  // no B: read A's gap
-        const uint32_t o = (tid - cpre[lo]) * CI;
+        const uint32_t o = (tid - cp[lo]) * CI;
         count = la + lb - o < (uint32_t)CI ? la + lb - o : (uint32_t)CI;
         start = a0 + o;
         last = o + count == la + lb;
         gap_at = a0 + la + lb;
         merge_chunk_keys<U, CI>(sk, a0, la, b0, lb, o, rk);
       } else if (!GAPS && tid < nchunks) {
-        uint32_t lo = 0, hi = npairs;  // pair q with cpre[q] <= tid < cpre[q+1]
+        uint32_t lo = 0, hi = npairs;  // pair q with cp[q] <= tid < cp[q+1]
         while (hi - lo > 1) {
           const uint32_t mid = (lo + hi) >> 1;
-          if (cpre[mid] <= tid) lo = mid;
+          if (cp[mid] <= tid) lo = mid;
           else hi = mid;
         }
         const uint32_t s0 = 2 * w * lo;
         const uint32_t A0 = soff[s0];
         const uint32_t A1 = soff[s0 + w < F ? s0 + w : F];
         const uint32_t B1 = soff[s0 + 2 * w < F ? s0 + 2 * w : F];
-        start = A0 + (tid - cpre[lo]) * CI;
+        start = A0 + (tid - cp[lo]) * CI;
         count = B1 - start < (uint32_t)CI ? B1 - start : (uint32_t)CI;
         merge_chunk<U, KV, CI, false>(sk, sv, A0, A1, B1, start, rk, rv);
       }

@@ -268,6 +268,49 @@ __device__ __forceinline__ void merge_chunk_keys(const U *sk, uint32_t a0, uint3
   }
 }
 
+// Keys only: merge the sorted 16-key runs held by single lanes into sorted
+// 64-key runs held by groups of four lanes (lane j of a group then holds the
+// run's keys 16j..16j+15), with bitonic merge networks: a "flip" stage pairs
+// key i of the lower run with key n-1-i of the upper one across lanes, then
+// half-cleaners at falling distances, the last four inside each lane.
+template <typename U>
+__device__ __forceinline__ void inlane_half_cleaners(U (&k)[kTileItems]) {
+#pragma unroll
+  for (int d = kTileItems / 2; d >= 1; d >>= 1) {
+#pragma unroll
+    for (int i = 0; i < kTileItems; ++i) {
+      if ((i & d) == 0) {
+        const U a = k[i], b = k[i + d];
+        const bool sw = b < a;
+        k[i] = sw ? b : a;
+        k[i + d] = sw ? a : b;
+      }
+    }
+  }
+}
+
+template <typename U>
+__device__ __forceinline__ void cross_lane_stage(U (&k)[kTileItems], int mask, bool flip,
+                                                 bool upper) {
+  U o[kTileItems];
+#pragma unroll
+  for (int i = 0; i < kTileItems; ++i) o[i] = __shfl_xor(k[flip ? kTileItems - 1 - i : i], mask, 64);
+#pragma unroll
+  for (int i = 0; i < kTileItems; ++i) {
+    const bool lt = o[i] < k[i];
+    k[i] = (lt != upper) ? o[i] : k[i];  // lower lane keeps the minimum, upper the maximum
+  }
+}
+
+template <typename U>
+__device__ __forceinline__ void lane_runs_to_64(U (&k)[kTileItems], uint32_t lane) {
+  cross_lane_stage(k, 1, true, (lane & 1) != 0);   // runs of 16 -> 32
+  inlane_half_cleaners(k);
+  cross_lane_stage(k, 3, true, (lane & 2) != 0);   // runs of 32 -> 64
+  cross_lane_stage(k, 1, false, (lane & 1) != 0);
+  inlane_half_cleaners(k);
+}
+
 // --------------------------------------------------------------- K1 -------
 // One workgroup sorts one tile of at most kTile keys of one segment.  Keys are
 // mapped on load (K0), each thread sorts 16 consecutive keys in registers, then
@@ -297,8 +340,13 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
     TileArgs<typename Key<KT>::U> ta) {
   using U = typename Key<KT>::U;
   constexpr uint32_t TILE = THREADS * kTileItems;
-  // padded layout of TILE slots, plus the slack a merge chunk may read
-  constexpr uint32_t P = TILE + TILE / 16 + 2 * kRoundItems + 2;
+  // Key-value tiles: the padded layout of TILE slots.  Keys-only tiles: also
+  // every wave's region of gapped runs (see below).  Both plus the slack a
+  // merge chunk may read.
+  constexpr uint32_t RW = 64 * kTileItems + (64 * kTileItems / 128) * kGap;
+  constexpr uint32_t PADDED = TILE + TILE / 16;
+  constexpr uint32_t GAPPED = (THREADS / 64) * RW;
+  constexpr uint32_t P = (KV || PADDED > GAPPED ? PADDED : GAPPED) + 2 * kRoundItems + 2;
   __shared__ U sk[P];
   __shared__ uint32_t sv[KV ? P : 1];
 
@@ -364,75 +412,144 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
     if constexpr (KV) rv[i] = sv[pad16(idx)];
   }
   register_sort<U, KV, kTileItems>(rk, rv);
-  // every wave writes back the keys it read (its own 1024 positions)
-  wave_sync();
-#pragma unroll
-  for (int i = 0; i < kTileItems; ++i) {
-    const uint32_t idx = tid * kTileItems + i;
-    sk[pad16(idx)] = rk[i];
-    if constexpr (KV) sv[pad16(idx)] = rv[i];
-  }
-  wave_sync();
-
-  // Rounds of pairwise merges of runs of L keys.  Each pair's output is cut
-  // into chunks of CI keys (never crossing into the next pair), one chunk per
-  // thread: at most THREADS chunks per round.  The first round reads the
-  // padded layout; every round writes the flat one (CI is odd, so the
-  // threads' chunk stores do not collide in LDS banks).  While a pair fits in
-  // the 1024 keys that one wave's threads sorted, each wave merges only its
-  // own keys and, after the first round, synchronises only with itself.
-  constexpr int CI = kRoundItems;
-  constexpr uint32_t WKEYS = 64 * kTileItems;  // keys per wave
-  U mk[CI];
-  uint32_t mv[KV ? CI : 1];
-  const uint32_t lane = tid & 63, wbase = (tid >> 6) * WKEYS;
-  uint32_t L = kTileItems;
-  for (; L < TILE && 2 * L <= WKEYS; L *= 2) {
-    const uint32_t cpp = (2 * L + CI - 1) / CI;  // chunks per pair
-    const uint32_t q = lane / cpp, c = lane - q * cpp;
-    const bool active = q < WKEYS / (2 * L);
-    const uint32_t A0 = wbase + q * 2 * L;
-    const uint32_t cs = A0 + c * CI;  // this thread's first output
-    const uint32_t count = active ? (A0 + 2 * L - cs < (uint32_t)CI ? A0 + 2 * L - cs : CI) : 0;
-    if (active) {
-      if (L == kTileItems)
-        merge_chunk<U, KV, CI, true>(sk, sv, A0, A0 + L, A0 + 2 * L, cs, mk, mv);
-      else
-        merge_chunk<U, KV, CI, false>(sk, sv, A0, A0 + L, A0 + 2 * L, cs, mk, mv);
-    }
-    // The first round moves every wave's keys from the padded layout to the
-    // flat one, whose slots overlap the previous wave's padded ones: all
-    // waves must finish reading first.  Later rounds stay in the wave's own
-    // flat slots.
-    if (L == kTileItems) __syncthreads();
-    else wave_sync();
-#pragma unroll
-    for (int i = 0; i < CI; ++i) {
-      if ((uint32_t)i < count) {
-        sk[cs + i] = mk[i];
-        if constexpr (KV) sv[cs + i] = mv[i];
-      }
+  if constexpr (KV) {
+    // every wave writes back the keys it read (its own 1024 positions)
+    wave_sync();
+  #pragma unroll
+    for (int i = 0; i < kTileItems; ++i) {
+      const uint32_t idx = tid * kTileItems + i;
+      sk[pad16(idx)] = rk[i];
+      if constexpr (KV) sv[pad16(idx)] = rv[i];
     }
     wave_sync();
-  }
-  __syncthreads();
-  for (; L < TILE; L *= 2) {
-    const uint32_t cpp = (2 * L + CI - 1) / CI;  // chunks per pair
-    const uint32_t q = tid / cpp, c = tid - q * cpp;
-    const uint32_t A0 = q * 2 * L;
-    const bool active = A0 < TILE;
-    const uint32_t cs = A0 + c * CI;  // this thread's first output
-    const uint32_t count = active ? (A0 + 2 * L - cs < (uint32_t)CI ? A0 + 2 * L - cs : CI) : 0;
-    if (active) merge_chunk<U, KV, CI, false>(sk, sv, A0, A0 + L, A0 + 2 * L, cs, mk, mv);
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < CI; ++i) {
-      if ((uint32_t)i < count) {
-        sk[cs + i] = mk[i];
-        if constexpr (KV) sv[cs + i] = mv[i];
+
+    // Rounds of pairwise merges of runs of L keys.  Each pair's output is cut
+    // into chunks of CI keys (never crossing into the next pair), one chunk per
+    // thread: at most THREADS chunks per round.  The first round reads the
+    // padded layout; every round writes the flat one (CI is odd, so the
+    // threads' chunk stores do not collide in LDS banks).  While a pair fits in
+    // the 1024 keys that one wave's threads sorted, each wave merges only its
+    // own keys and, after the first round, synchronises only with itself.
+    constexpr int CI = kRoundItems;
+    constexpr uint32_t WKEYS = 64 * kTileItems;  // keys per wave
+    U mk[CI];
+    uint32_t mv[KV ? CI : 1];
+    const uint32_t lane = tid & 63, wbase = (tid >> 6) * WKEYS;
+    uint32_t L = kTileItems;
+    for (; L < TILE && 2 * L <= WKEYS; L *= 2) {
+      const uint32_t cpp = (2 * L + CI - 1) / CI;  // chunks per pair
+      const uint32_t q = lane / cpp, c = lane - q * cpp;
+      const bool active = q < WKEYS / (2 * L);
+      const uint32_t A0 = wbase + q * 2 * L;
+      const uint32_t cs = A0 + c * CI;  // this thread's first output
+      const uint32_t count = active ? (A0 + 2 * L - cs < (uint32_t)CI ? A0 + 2 * L - cs : CI) : 0;
+      if (active) {
+        if (L == kTileItems)
+          merge_chunk<U, KV, CI, true>(sk, sv, A0, A0 + L, A0 + 2 * L, cs, mk, mv);
+        else
+          merge_chunk<U, KV, CI, false>(sk, sv, A0, A0 + L, A0 + 2 * L, cs, mk, mv);
       }
+      // The first round moves every wave's keys from the padded layout to the
+      // flat one, whose slots overlap the previous wave's padded ones: all
+      // waves must finish reading first.  Later rounds stay in the wave's own
+      // flat slots.
+      if (L == kTileItems) __syncthreads();
+      else wave_sync();
+  #pragma unroll
+      for (int i = 0; i < CI; ++i) {
+        if ((uint32_t)i < count) {
+          sk[cs + i] = mk[i];
+          if constexpr (KV) sv[cs + i] = mv[i];
+        }
+      }
+      wave_sync();
     }
     __syncthreads();
+    for (; L < TILE; L *= 2) {
+      const uint32_t cpp = (2 * L + CI - 1) / CI;  // chunks per pair
+      const uint32_t q = tid / cpp, c = tid - q * cpp;
+      const uint32_t A0 = q * 2 * L;
+      const bool active = A0 < TILE;
+      const uint32_t cs = A0 + c * CI;  // this thread's first output
+      const uint32_t count = active ? (A0 + 2 * L - cs < (uint32_t)CI ? A0 + 2 * L - cs : CI) : 0;
+      if (active) merge_chunk<U, KV, CI, false>(sk, sv, A0, A0 + L, A0 + 2 * L, cs, mk, mv);
+      __syncthreads();
+  #pragma unroll
+      for (int i = 0; i < CI; ++i) {
+        if ((uint32_t)i < count) {
+          sk[cs + i] = mk[i];
+          if constexpr (KV) sv[cs + i] = mv[i];
+        }
+      }
+      __syncthreads();
+    }
+  } else {
+    // Keys only.  Runs of 64 are formed in registers (bitonic merges across
+    // lanes), written to the padded layout of each thread's own 16 slots.
+    lane_runs_to_64(rk, tid & 63);
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < kTileItems; ++i) sk[pad16(tid * kTileItems + i)] = rk[i];
+    wave_sync();
+    // Then rounds of merge-path merges.  Round 64 reads the padded layout and
+    // writes the gapped one, where every run is followed by kGap slots of the
+    // largest key, so the later rounds use merge_chunk_keys (no bound
+    // checks).  While a pair fits in one wave's 1024 keys, runs of length L
+    // sit at q (L + G) in the wave's own region of RW slots and the wave
+    // synchronises only with itself; larger rounds use runs at j (L + G)
+    // across the tile.
+    constexpr int CI = kRoundItems;
+    constexpr uint32_t G = kGap, WKEYS = 64 * kTileItems;
+    const uint32_t lane = tid & 63, wv = tid >> 6;
+    U mk[CI];
+    uint32_t dummy_v[1];
+    uint32_t L = 64;
+    for (; L < TILE && 2 * L <= WKEYS; L *= 2) {
+      const uint32_t cpp = (2 * L + CI - 1) / CI;  // chunks per pair
+      const uint32_t q = lane / cpp, c = lane - q * cpp;
+      const bool active = q < WKEYS / (2 * L);
+      const uint32_t o = c * CI;  // this chunk's first output within the pair
+      const uint32_t count = active ? (2 * L - o < (uint32_t)CI ? 2 * L - o : CI) : 0u;
+      const bool to_tile = 4 * L > WKEYS;  // the next round's pairs span waves
+      const uint32_t dst = to_tile ? (wv * (WKEYS / (2 * L)) + q) * (2 * L + G)
+                                   : wv * RW + q * (2 * L + G);
+      if (active) {
+        if (L == 64) {
+          const uint32_t A0 = wv * WKEYS + q * 2 * L;
+          merge_chunk<U, false, CI, true>(sk, sv, A0, A0 + L, A0 + 2 * L, A0 + o, mk, dummy_v);
+        } else {
+          const uint32_t A0 = wv * RW + 2 * q * (L + G);
+          merge_chunk_keys<U, CI>(sk, A0, L, A0 + L + G, L, o, mk);
+        }
+      }
+      // round 64 leaves the padded layout, whose slots overlap other waves'
+      // regions; a round writing tile-wide runs leaves the wave's region
+      if (L == 64 || to_tile) __syncthreads();
+      else wave_sync();
+#pragma unroll
+      for (int i = 0; i < CI; ++i)
+        if ((uint32_t)i < count) sk[dst + o + i] = mk[i];
+      if (active && o + count == 2 * L)
+        for (uint32_t j = 0; j < G; ++j) sk[dst + 2 * L + j] = key_max<U>();
+      if (to_tile) __syncthreads();
+      else wave_sync();
+    }
+    for (; L < TILE; L *= 2) {
+      const uint32_t cpp = (2 * L + CI - 1) / CI;  // chunks per pair
+      const uint32_t q = tid / cpp, c = tid - q * cpp;
+      const bool active = q < TILE / (2 * L);
+      const uint32_t o = c * CI;
+      const uint32_t count = active ? (2 * L - o < (uint32_t)CI ? 2 * L - o : CI) : 0u;
+      const uint32_t A0 = 2 * q * (L + G), dst = q * (2 * L + G);
+      if (active) merge_chunk_keys<U, CI>(sk, A0, L, A0 + L + G, L, o, mk);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < CI; ++i)
+        if ((uint32_t)i < count) sk[dst + o + i] = mk[i];
+      if (active && o + count == 2 * L && 2 * L < TILE)
+        for (uint32_t j = 0; j < G; ++j) sk[dst + 2 * L + j] = key_max<U>();
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int i = 0; i < kTileItems; ++i) {
@@ -1189,8 +1306,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
   }
 
   if constexpr (MAXF <= 64) {
-    // one wave: segment sizes, their exclusive scan, and the chunk prefix
-    // of every merge round (from registers, so no other wave waits on it)
+    // one wave: segment sizes and their exclusive scan
     if (tid < 64) {
       uint32_t c = 0;
       if (tid < F) {
@@ -1211,26 +1327,6 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
       const uint32_t total = __shfl(x, 63, 64);
       if (tid < F) soff[tid] = e;
       if (tid == 0) soff[F] = total;
-      auto off_at = [&](uint32_t j) {  // soff[j] for j <= F (all lanes take part)
-        const uint32_t v = __shfl(e, (int)(j < 64 ? j : 63), 64);
-        return j < 64 ? v : total;
-      };
-      uint32_t r = 0;
-      for (uint32_t w = 1; w < F; w <<= 1, ++r) {
-        const uint32_t np = (F + 2 * w - 1) / (2 * w);
-        const uint32_t j0 = 2 * w * tid < F ? 2 * w * tid : F;
-        const uint32_t j1 = 2 * w * tid + 2 * w < F ? 2 * w * tid + 2 * w : F;
-        const uint32_t a0 = off_at(j0), b1 = off_at(j1);
-        const uint32_t cc = tid < np ? (b1 - a0 + kRoundItems - 1) / kRoundItems : 0u;
-        uint32_t xc = cc;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-          const uint32_t y = __shfl_up(xc, d, 64);
-          if ((int)tid >= d) xc += y;
-        }
-        if (tid < np) cpre[r * 33 + tid] = xc - cc;
-        if (tid == np - 1) cpre[r * 33 + np] = xc;
-      }
     }
     __syncthreads();
   } else {
@@ -1314,6 +1410,34 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
       kreg[i] = idx < M ? src[addr[i]] : U(0);
       if constexpr (VMODE == 1) vreg[i] = idx < M ? vsrc[addr[i]] : 0u;
       if constexpr (VMODE == 2) vreg[i] = runid[i];
+    }
+    if constexpr (MAXF <= 64) {
+      // While its loads are in flight, wave 0 computes the chunk prefix over
+      // pairs of every merge round (published by the barrier below).
+      if (tid < 64) {
+        const uint32_t e = soff[tid < F ? tid : F];
+        const uint32_t total = soff[F];
+        auto off_at = [&](uint32_t j) {  // soff[j] for j <= F (all lanes take part)
+          const uint32_t v = __shfl(e, (int)(j < 64 ? j : 63), 64);
+          return j < 64 ? v : total;
+        };
+        uint32_t r = 0;
+        for (uint32_t w = 1; w < F; w <<= 1, ++r) {
+          const uint32_t np = (F + 2 * w - 1) / (2 * w);
+          const uint32_t j0 = 2 * w * tid < F ? 2 * w * tid : F;
+          const uint32_t j1 = 2 * w * tid + 2 * w < F ? 2 * w * tid + 2 * w : F;
+          const uint32_t a0 = off_at(j0), b1 = off_at(j1);
+          const uint32_t cc = tid < np ? (b1 - a0 + kRoundItems - 1) / kRoundItems : 0u;
+          uint32_t xc = cc;
+#pragma unroll
+          for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(xc, d, 64);
+            if ((int)tid >= d) xc += y;
+          }
+          if (tid < np) cpre[r * 33 + tid] = xc - cc;
+          if (tid == np - 1) cpre[r * 33 + np] = xc;
+        }
+      }
     }
 #pragma unroll
     for (int i = 0; i < kMergeItems; ++i) {

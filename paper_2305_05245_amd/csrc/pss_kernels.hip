@@ -269,10 +269,11 @@ __device__ __forceinline__ void merge_chunk_keys(const U *sk, uint32_t a0, uint3
 }
 
 // Keys only: merge the sorted 16-key runs held by single lanes into sorted
-// 64-key runs held by groups of four lanes (lane j of a group then holds the
+// 128-key runs held by groups of eight lanes (lane j of a group then holds the
 // run's keys 16j..16j+15), with bitonic merge networks: a "flip" stage pairs
 // key i of the lower run with key n-1-i of the upper one across lanes, then
-// half-cleaners at falling distances, the last four inside each lane.
+// half-cleaners at falling distances, the last four inside each lane.  Lane
+// exchanges use DPP moves (quad permutations and the half-row mirror).
 template <typename U>
 __device__ __forceinline__ void inlane_half_cleaners(U (&k)[kTileItems]) {
 #pragma unroll
@@ -289,12 +290,28 @@ __device__ __forceinline__ void inlane_half_cleaners(U (&k)[kTileItems]) {
   }
 }
 
-template <typename U>
-__device__ __forceinline__ void cross_lane_stage(U (&k)[kTileItems], int mask, bool flip,
-                                                 bool upper) {
+// x from the lane given by the DPP control CTRL (all lanes active)
+template <int CTRL, typename U>
+__device__ __forceinline__ U dpp_from(U x) {
+  if constexpr (sizeof(U) == 8) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, 0xF, 0xF, false);
+    return ((U)(uint32_t)hi << 32) | (U)(uint32_t)lo;
+  } else {
+    return (U)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+  }
+}
+
+constexpr int kDppXor1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int kDppXor3 = 0x1B;  // quad_perm [3,2,1,0]
+constexpr int kDppXor7 = 0x141; // row_half_mirror: lane i of 8 reads lane 7-i
+
+template <int CTRL, bool FLIP, typename U>
+__device__ __forceinline__ void cross_lane_stage(U (&k)[kTileItems], bool upper) {
   U o[kTileItems];
 #pragma unroll
-  for (int i = 0; i < kTileItems; ++i) o[i] = __shfl_xor(k[flip ? kTileItems - 1 - i : i], mask, 64);
+  for (int i = 0; i < kTileItems; ++i) o[i] = dpp_from<CTRL>(k[FLIP ? kTileItems - 1 - i : i]);
 #pragma unroll
   for (int i = 0; i < kTileItems; ++i) {
     const bool lt = o[i] < k[i];
@@ -303,11 +320,15 @@ __device__ __forceinline__ void cross_lane_stage(U (&k)[kTileItems], int mask, b
 }
 
 template <typename U>
-__device__ __forceinline__ void lane_runs_to_64(U (&k)[kTileItems], uint32_t lane) {
-  cross_lane_stage(k, 1, true, (lane & 1) != 0);   // runs of 16 -> 32
+__device__ __forceinline__ void lane_runs_to_128(U (&k)[kTileItems], uint32_t lane) {
+  cross_lane_stage<kDppXor1, true>(k, (lane & 1) != 0);  // runs of 16 -> 32
   inlane_half_cleaners(k);
-  cross_lane_stage(k, 3, true, (lane & 2) != 0);   // runs of 32 -> 64
-  cross_lane_stage(k, 1, false, (lane & 1) != 0);
+  cross_lane_stage<kDppXor3, true>(k, (lane & 2) != 0);  // runs of 32 -> 64
+  cross_lane_stage<kDppXor1, false>(k, (lane & 1) != 0);
+  inlane_half_cleaners(k);
+  cross_lane_stage<kDppXor7, true>(k, (lane & 4) != 0);  // runs of 64 -> 128
+  cross_lane_stage<kDppXor2, false>(k, (lane & 2) != 0);
+  cross_lane_stage<kDppXor1, false>(k, (lane & 1) != 0);
   inlane_half_cleaners(k);
 }
 
@@ -343,10 +364,16 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
   // Key-value tiles: the padded layout of TILE slots.  Keys-only tiles: also
   // every wave's region of gapped runs (see below).  Both plus the slack a
   // merge chunk may read.
-  constexpr uint32_t RW = 64 * kTileItems + (64 * kTileItems / 128) * kGap;
+  constexpr uint32_t RW = 64 * kTileItems + (64 * kTileItems / 256) * kGap;
   constexpr uint32_t PADDED = TILE + TILE / 16;
   constexpr uint32_t GAPPED = (THREADS / 64) * RW;
   constexpr uint32_t P = (KV || PADDED > GAPPED ? PADDED : GAPPED) + 2 * kRoundItems + 2;
+  // Padded layout (one spare slot per 16 keys).  Keys-only tiles place each
+  // wave's 1024 keys at the start of that wave's region of RW slots, so the
+  // wave later merges from the padded into the gapped layout on its own.
+  auto tile_pad = [](uint32_t idx) -> uint32_t {
+    return KV ? pad16(idx) : (idx >> 10) * RW + pad16(idx & 1023u);
+  };
   __shared__ U sk[P];
   __shared__ uint32_t sv[KV ? P : 1];
 
@@ -398,7 +425,7 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
 #pragma unroll
   for (int i = 0; i < kTileItems; ++i) {
     const uint32_t idx = i * THREADS + tid;
-    sk[pad16(idx)] = idx < len ? Key<KT>::map(raw[i]) : key_max<U>();
+    sk[tile_pad(idx)] = idx < len ? Key<KT>::map(raw[i]) : key_max<U>();
     if constexpr (KV) sv[pad16(idx)] = idx < len ? vraw[i] : 0u;
   }
   __syncthreads();
@@ -408,7 +435,7 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
 #pragma unroll
   for (int i = 0; i < kTileItems; ++i) {
     const uint32_t idx = tid * kTileItems + i;
-    rk[i] = sk[pad16(idx)];
+    rk[i] = sk[tile_pad(idx)];
     if constexpr (KV) rv[i] = sv[pad16(idx)];
   }
   register_sort<U, KV, kTileItems>(rk, rv);
@@ -484,14 +511,14 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
       __syncthreads();
     }
   } else {
-    // Keys only.  Runs of 64 are formed in registers (bitonic merges across
+    // Keys only.  Runs of 128 are formed in registers (bitonic merges across
     // lanes), written to the padded layout of each thread's own 16 slots.
-    lane_runs_to_64(rk, tid & 63);
+    lane_runs_to_128(rk, tid & 63);
     wave_sync();
 #pragma unroll
-    for (int i = 0; i < kTileItems; ++i) sk[pad16(tid * kTileItems + i)] = rk[i];
+    for (int i = 0; i < kTileItems; ++i) sk[tile_pad(tid * kTileItems + i)] = rk[i];
     wave_sync();
-    // Then rounds of merge-path merges.  Round 64 reads the padded layout and
+    // Then rounds of merge-path merges.  Round 128 reads the padded layout and
     // writes the gapped one, where every run is followed by kGap slots of the
     // largest key, so the later rounds use merge_chunk_keys (no bound
     // checks).  While a pair fits in one wave's 1024 keys, runs of length L
@@ -503,7 +530,7 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
     const uint32_t lane = tid & 63, wv = tid >> 6;
     U mk[CI];
     uint32_t dummy_v[1];
-    uint32_t L = 64;
+    uint32_t L = 128;
     for (; L < TILE && 2 * L <= WKEYS; L *= 2) {
       const uint32_t cpp = (2 * L + CI - 1) / CI;  // chunks per pair
       const uint32_t q = lane / cpp, c = lane - q * cpp;
@@ -514,17 +541,18 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
       const uint32_t dst = to_tile ? (wv * (WKEYS / (2 * L)) + q) * (2 * L + G)
                                    : wv * RW + q * (2 * L + G);
       if (active) {
-        if (L == 64) {
-          const uint32_t A0 = wv * WKEYS + q * 2 * L;
-          merge_chunk<U, false, CI, true>(sk, sv, A0, A0 + L, A0 + 2 * L, A0 + o, mk, dummy_v);
+        if (L == 128) {
+          // padded layout of the wave's keys at the start of its region
+          const uint32_t A0 = q * 2 * L;
+          merge_chunk<U, false, CI, true>(sk + wv * RW, sv, A0, A0 + L, A0 + 2 * L, A0 + o, mk,
+                                          dummy_v);
         } else {
           const uint32_t A0 = wv * RW + 2 * q * (L + G);
           merge_chunk_keys<U, CI>(sk, A0, L, A0 + L + G, L, o, mk);
         }
       }
-      // round 64 leaves the padded layout, whose slots overlap other waves'
-      // regions; a round writing tile-wide runs leaves the wave's region
-      if (L == 64 || to_tile) __syncthreads();
+      // a round writing tile-wide runs leaves the wave's region
+      if (to_tile) __syncthreads();
       else wave_sync();
 #pragma unroll
       for (int i = 0; i < CI; ++i)

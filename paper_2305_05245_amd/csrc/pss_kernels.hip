@@ -306,6 +306,33 @@ constexpr int kDppXor1 = 0xB1;  // quad_perm [1,0,3,2]
 constexpr int kDppXor2 = 0x4E;  // quad_perm [2,3,0,1]
 constexpr int kDppXor3 = 0x1B;  // quad_perm [3,2,1,0]
 constexpr int kDppXor7 = 0x141; // row_half_mirror: lane i of 8 reads lane 7-i
+constexpr int kDppRor8 = 0x128; // row_ror:8: lane i of 16 reads lane i xor 8
+
+// x from lane (lane xor 16) within each half of the wave (swizzle unit)
+template <typename T>
+__device__ __forceinline__ T swizzle_xor16(T x) {
+  constexpr int kPattern = (0x10 << 10) | 0x1F;  // bit mode: and 0x1f, or 0, xor 0x10
+  if constexpr (sizeof(T) == 8) {
+    const int lo = __builtin_amdgcn_ds_swizzle((int)(uint32_t)x, kPattern);
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(uint32_t)((uint64_t)x >> 32), kPattern);
+    return (T)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+  } else {
+    return (T)__builtin_amdgcn_ds_swizzle((int)x, kPattern);
+  }
+}
+
+// x from lane (lane xor D): DPP moves for D <= 8 (xor 4 is the half-row
+// mirror followed by the quad reversal), the swizzle unit for 16, a full
+// cross-lane permute beyond
+template <int D, typename T>
+__device__ __forceinline__ T shfl_xor_c(T x) {
+  if constexpr (D == 1) return dpp_from<kDppXor1>(x);
+  else if constexpr (D == 2) return dpp_from<kDppXor2>(x);
+  else if constexpr (D == 4) return dpp_from<kDppXor3>(dpp_from<kDppXor7>(x));
+  else if constexpr (D == 8) return dpp_from<kDppRor8>(x);
+  else if constexpr (D == 16) return swizzle_xor16(x);
+  else return __shfl_xor(x, D, 64);
+}
 
 template <int CTRL, bool FLIP, typename U>
 __device__ __forceinline__ void cross_lane_stage(U (&k)[kTileItems], bool upper) {
@@ -968,6 +995,28 @@ __device__ __forceinline__ void cas(U &ka, uint32_t &ta, U &kb, uint32_t &tb, bo
   }
 }
 
+// One compare-exchange stage of the wave's bitonic sort at lane distance D
+// (slot s = lane + 64 e; sort block k; ascending by (key, tie)).
+template <int D, typename U, int E>
+__device__ __forceinline__ void bitonic_lane_stage(U (&key)[E], uint32_t (&tie)[E], uint32_t lane,
+                                                   uint32_t k, uint32_t Cp) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (64u * e < Cp) {
+      const U ok = shfl_xor_c<D>(key[e]);
+      const uint32_t ot = shfl_xor_c<D>(tie[e]);
+      const uint32_t idx = lane + 64u * e;
+      const bool lower = (lane & D) == 0;
+      const bool up = (idx & k) == 0;
+      const bool mine_gt = key[e] > ok || (key[e] == ok && tie[e] > ot);
+      // the lower slot keeps the smaller when ascending
+      const bool take_other = (lower == up) ? mine_gt : !mine_gt;
+      key[e] = take_other ? ok : key[e];
+      tie[e] = take_other ? ot : tie[e];
+    }
+  }
+}
+
 // Merged samples of one pass: the group's level-kSampleLog2 samples in
 // (key, run, position) order as run ids, plus per-run prefix counts at every
 // kChunk-th merged sample.  They give V_5(Q) for any Q without a search.
@@ -1099,37 +1148,26 @@ __global__ __launch_bounds__(kCorankThreads) void corank_wave_kernel(
         }
       }
 
-      // bitonic sort of Cp slots, ascending by (key, tie)
+      // bitonic sort of Cp slots, ascending by (key, tie): distances of 64
+      // and more exchange slots inside a lane, smaller ones exchange lanes
       for (uint32_t k = 2; k <= Cp; k <<= 1) {
-        for (uint32_t d = k >> 1; d > 0; d >>= 1) {
-          if (d >= 64) {
-            const uint32_t de = d >> 6;
+        for (uint32_t d = k >> 1; d >= 64; d >>= 1) {
+          const uint32_t de = d >> 6;
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-              if (E > 1 && ((uint32_t)e & de) == 0 && (e | (int)de) < E && 64u * (e | de) < Cp) {
-                const bool up = ((lane + 64u * e) & k) == 0;
-                if (de == 1) cas<U, E>(key[e], tie[e], key[e | 1], tie[e | 1], up);
-                else if (de == 2) cas<U, E>(key[e], tie[e], key[(e | 2) & (E - 1)], tie[(e | 2) & (E - 1)], up);
-              }
-            }
-          } else {
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-              if (64u * e < Cp) {
-                const U ok = __shfl_xor(key[e], (int)d, 64);
-                const uint32_t ot = __shfl_xor(tie[e], (int)d, 64);
-                const uint32_t idx = lane + 64u * e;
-                const bool lower = (lane & d) == 0;
-                const bool up = (idx & k) == 0;
-                const bool mine_gt = key[e] > ok || (key[e] == ok && tie[e] > ot);
-                // the lower slot keeps the smaller when ascending
-                const bool take_other = (lower == up) ? mine_gt : !mine_gt;
-                key[e] = take_other ? ok : key[e];
-                tie[e] = take_other ? ot : tie[e];
-              }
+          for (int e = 0; e < E; ++e) {
+            if (E > 1 && ((uint32_t)e & de) == 0 && (e | (int)de) < E && 64u * (e | de) < Cp) {
+              const bool up = ((lane + 64u * e) & k) == 0;
+              if (de == 1) cas<U, E>(key[e], tie[e], key[e | 1], tie[e | 1], up);
+              else if (de == 2) cas<U, E>(key[e], tie[e], key[(e | 2) & (E - 1)], tie[(e | 2) & (E - 1)], up);
             }
           }
         }
+        if (k > 32) bitonic_lane_stage<32>(key, tie, lane, k, Cp);
+        if (k > 16) bitonic_lane_stage<16>(key, tie, lane, k, Cp);
+        if (k > 8) bitonic_lane_stage<8>(key, tie, lane, k, Cp);
+        if (k > 4) bitonic_lane_stage<4>(key, tie, lane, k, Cp);
+        if (k > 2) bitonic_lane_stage<2>(key, tie, lane, k, Cp);
+        bitonic_lane_stage<1>(key, tie, lane, k, Cp);
       }
 
       uint64_t rho_lo = q_lo - base, rho_hi = q_hi - base;

@@ -581,11 +581,14 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
       // a round writing tile-wide runs leaves the wave's region
       if (to_tile) __syncthreads();
       else wave_sync();
+      // every active chunk stores all CI keys: a pair's last chunk spills
+      // into the run's new gap, which it then fills with the largest key
+      if (active) {
 #pragma unroll
-      for (int i = 0; i < CI; ++i)
-        if ((uint32_t)i < count) sk[dst + o + i] = mk[i];
-      if (active && o + count == 2 * L)
-        for (uint32_t j = 0; j < G; ++j) sk[dst + 2 * L + j] = key_max<U>();
+        for (int i = 0; i < CI; ++i) sk[dst + o + i] = mk[i];
+        if (o + count == 2 * L)
+          for (uint32_t j = 0; j < G; ++j) sk[dst + 2 * L + j] = key_max<U>();
+      }
       if (to_tile) __syncthreads();
       else wave_sync();
     }
@@ -598,11 +601,12 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
       const uint32_t A0 = 2 * q * (L + G), dst = q * (2 * L + G);
       if (active) merge_chunk_keys<U, CI>(sk, A0, L, A0 + L + G, L, o, mk);
       __syncthreads();
+      if (active) {
 #pragma unroll
-      for (int i = 0; i < CI; ++i)
-        if ((uint32_t)i < count) sk[dst + o + i] = mk[i];
-      if (active && o + count == 2 * L && 2 * L < TILE)
-        for (uint32_t j = 0; j < G; ++j) sk[dst + 2 * L + j] = key_max<U>();
+        for (int i = 0; i < CI; ++i) sk[dst + o + i] = mk[i];
+        if (o + count == 2 * L && 2 * L < TILE)
+          for (uint32_t j = 0; j < G; ++j) sk[dst + 2 * L + j] = key_max<U>();
+      }
       __syncthreads();
     }
   }
@@ -1575,16 +1579,24 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
         merge_chunk<U, KV, CI, false>(sk, sv, A0, A1, B1, start, rk, rv);
       }
       __syncthreads();
+      if (GAPS) {
+        // A pair's last chunk computes its outputs past the pair's end from
+        // the gaps (the largest key) and stores them into the run's new gap,
+        // which it then fills anyway: every active chunk stores all CI keys.
+        if (count) {
 #pragma unroll
-      for (int i = 0; i < CI; ++i) {
-        if ((uint32_t)i < count) {
-          sk[start + i] = rk[i];
-          if constexpr (KV) sv[start + i] = rv[i];
+          for (int i = 0; i < CI; ++i) sk[start + i] = rk[i];
+          if (last)
+            for (uint32_t j = 0; j < G; ++j) sk[gap_at + j] = key_max<U>();
         }
-      }
-      if (GAPS && last) {
-        // the merged run's gap (the pair's region has room for it)
-        for (uint32_t j = 0; j < G; ++j) sk[gap_at + j] = key_max<U>();
+      } else {
+#pragma unroll
+        for (int i = 0; i < CI; ++i) {
+          if ((uint32_t)i < count) {
+            sk[start + i] = rk[i];
+            if constexpr (KV) sv[start + i] = rv[i];
+          }
+        }
       }
       __syncthreads();
     }

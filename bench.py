@@ -114,6 +114,32 @@ def cpu_baseline(log2n: int = 25):
                       f"{dt:.1f} s"}
 
 
+def bench_key_value(pss, torch, log2n: int, steps: int, warmup: int) -> dict:
+    """2^log2n uniform u64 keys with their uint32 input index as value (the
+    serving loop's record), stable key-value sort, data resident in HBM."""
+    import numpy as np
+
+    import workloads as W
+    from paper_2305_05245_amd import _lib
+
+    n = 1 << log2n
+    keys = torch.from_numpy(W.uniform_u64(n, seed=2).view(np.int64)).cuda()
+    vals = torch.arange(n, dtype=torch.int32, device="cuda")
+    ko, vo = torch.empty_like(keys), torch.empty_like(vals)
+    ws = torch.empty(_lib.workspace_bytes(_lib.U64, _lib.VAL_U32, n), dtype=torch.uint8,
+                     device="cuda")
+    for _ in range(warmup):
+        pss.sort(keys, vals, key_type="u64", out=ko, vals_out=vo, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pss.sort(keys, vals, key_type="u64", out=ko, vals_out=vo, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"workload": f"2^{log2n} uniform u64 keys + u32 index values, stable",
+            "ms": round(dt * 1e3, 3), "gkeys_per_s": round(n / dt / 1e9, 3)}
+
+
 def bench_batched(pss, torch, steps: int, warmup: int) -> dict:
     """4096 int64 arrays of round(2^U) keys, U ~ Uniform[6, 20] (seed 12), keys
     uniform over the full range (seed 13): the segmented sort replayed from one
@@ -311,7 +337,7 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-array batch")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=20000)
-    ap.add_argument("--leg", choices=("batched", "serving"),
+    ap.add_argument("--leg", choices=("batched", "serving", "key_value"),
                     help="run only this leg and print its JSON object (for profiling)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a plain device-to-device copy of the keys (bandwidth and "
@@ -334,6 +360,10 @@ def main() -> int:
         return 1
     _lib.load()  # fail loudly when the HIP library is missing
 
+    if args.leg == "key_value":
+        print(json.dumps(bench_key_value(pss, torch, args.log2n, max(3, args.steps // 2), 1)),
+              flush=True)
+        return 0
     if args.leg == "batched":
         print(json.dumps(bench_batched(pss, torch, max(3, args.steps // 2), 1)), flush=True)
         return 0
@@ -433,6 +463,9 @@ def main() -> int:
     del keys, keys_dev, out, ws
     torch.cuda.empty_cache()
     if not args.no_batched:
+        print("[bench] key-value sort", file=sys.stderr, flush=True)
+        line["key_value"] = bench_key_value(pss, torch, args.log2n, max(3, args.steps // 2), 1)
+        torch.cuda.empty_cache()
         print("[bench] batched segmented sort", file=sys.stderr, flush=True)
         line["batched"] = bench_batched(pss, torch, max(3, args.steps // 2), 1)
         torch.cuda.empty_cache()

@@ -1328,13 +1328,19 @@ template <typename U> struct MergeBufs {
   uint32_t *vdst, *vdst_alt;
 };
 
-template <int KT, int VMODE, uint32_t MAXF>
-__global__ __launch_bounds__(kMergeThreads) void merge_kernel(
+template <int KT, int VMODE, uint32_t MAXF, uint32_t NT = kMergeThreads>
+__global__ __launch_bounds__(NT) void merge_kernel(
     MergeBufs<typename Key<KT>::U> bufs, RunGeom g, const uint32_t *__restrict__ table,
     const uint64_t *__restrict__ part_off, int final_pass,
     typename Key<KT>::U *__restrict__ samples, uint32_t *__restrict__ prefix) {
   using U = typename Key<KT>::U;
   constexpr bool KV = VMODE != 0;
+  // NT threads, ITEMS keys each; a merge round gives each thread a chunk of
+  // CI outputs (odd, and small enough that a round's chunks fit in NT)
+  constexpr int ITEMS = kPart / NT;
+  constexpr int CI = NT == NT ? kRoundItems : ITEMS + 1;
+  constexpr int LP = kPart / NT;  // positions each thread labels
+  static_assert(NT * ITEMS == kPart && CI % 2 == 1 && LP % 4 == 0, "merge geometry");
   // Keys-only merges of at most 32 runs leave kGap slots holding the largest
   // key after every segment in LDS (see merge_chunk_keys); others use the
   // flat layout.  Both add the slack a merge chunk may read past the end.
@@ -1348,7 +1354,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
   __shared__ uint32_t cpre[MAXF <= 64 ? 6 * 33 : 1];
   __shared__ uint64_t ssrc[MAXF];
   __shared__ uint32_t sseg[MAXF <= 64 ? kPart / 4 : 1];  // segment of each position, bytes
-  __shared__ uint32_t wsum[kMergeThreads / 64 + 1];
+  __shared__ uint32_t wsum[NT / 64 + 1];
   __shared__ uint32_t hist[VMODE == 2 ? (kPart / kChunk) * kMaxSampledFan : 1];
 
   const uint32_t tid = threadIdx.x;
@@ -1400,7 +1406,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
     }
     __syncthreads();
   } else {
-    for (uint32_t b = tid; b < F; b += kMergeThreads) {
+    for (uint32_t b = tid; b < F; b += NT) {
       const uint32_t lo = pi.lo_row[b], hi = pi.hi_row[b];
       const uint32_t len = run_length(pi.group_len, R, b);
       const bool ok = lo <= hi && hi <= len;
@@ -1420,40 +1426,42 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
   // gather the partition's segments (coalesced within each segment): first
   // every source address, then all loads back to back, then the LDS stores
   {
-    uint64_t addr[kMergeItems];
-    uint32_t runid[VMODE == 2 ? kMergeItems : 1];
-    uint32_t lpos[kMergeItems];  // LDS slot of each item
+    uint64_t addr[ITEMS];
+    uint32_t runid[VMODE == 2 ? ITEMS : 1];
+    uint32_t lpos[ITEMS];  // LDS slot of each item
     if constexpr (MAXF <= 64) {
       // Label every position with its segment (one byte each): thread t
       // labels positions 16t..16t+15, so each item below finds its segment
       // with one independent LDS read instead of a walk over the offsets.
-      const uint32_t p0 = tid * 16;
+      const uint32_t p0 = tid * LP;
       if (p0 < M) {
         uint32_t b = find_segment(soff, F, p0);
         uint32_t nxt = soff[b + 1];
-        uint32_t wd[4] = {0u, 0u, 0u, 0u};
+        uint32_t wd[LP / 4];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
+        for (int j = 0; j < LP / 4; ++j) wd[j] = 0u;
+#pragma unroll
+        for (int j = 0; j < LP; ++j) {
           if (p0 + j < M) {
             while (p0 + j >= nxt) nxt = soff[++b + 1];
           }
           wd[j >> 2] |= b << (8 * (j & 3));
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) sseg[tid * 4 + j] = wd[j];
+        for (int j = 0; j < LP / 4; ++j) sseg[tid * (LP / 4) + j] = wd[j];
       }
-      for (uint32_t b = tid; b < F; b += kMergeThreads) ssrc[b] -= soff[b];
+      for (uint32_t b = tid; b < F; b += NT) ssrc[b] -= soff[b];
       __syncthreads();
       const uint8_t *seg_of = reinterpret_cast<const uint8_t *>(sseg);
-      uint32_t bi[kMergeItems];
+      uint32_t bi[ITEMS];
 #pragma unroll
-      for (int i = 0; i < kMergeItems; ++i) {
-        const uint32_t idx = i * kMergeThreads + tid;
+      for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t idx = i * NT + tid;
         bi[i] = idx < M ? seg_of[idx] : 0u;
       }
 #pragma unroll
-      for (int i = 0; i < kMergeItems; ++i) {
-        const uint32_t idx = i * kMergeThreads + tid;
+      for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t idx = i * NT + tid;
         addr[i] = ssrc[bi[i]] + idx;
         lpos[i] = idx + bi[i] * G;
         if constexpr (VMODE == 2) runid[i] = bi[i];
@@ -1461,8 +1469,8 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
     } else {
       uint32_t b = tid < M ? find_segment(soff, F, tid) : 0;
 #pragma unroll
-      for (int i = 0; i < kMergeItems; ++i) {
-        const uint32_t idx = i * kMergeThreads + tid;
+      for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t idx = i * NT + tid;
         addr[i] = 0;
         if (idx < M) {
           while (soff[b + 1] <= idx) ++b;
@@ -1472,11 +1480,11 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
         if constexpr (VMODE == 2) runid[i] = b;
       }
     }
-    U kreg[kMergeItems];
-    uint32_t vreg[KV ? kMergeItems : 1];
+    U kreg[ITEMS];
+    uint32_t vreg[KV ? ITEMS : 1];
 #pragma unroll
-    for (int i = 0; i < kMergeItems; ++i) {
-      const uint32_t idx = i * kMergeThreads + tid;
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint32_t idx = i * NT + tid;
       kreg[i] = idx < M ? src[addr[i]] : U(0);
       if constexpr (VMODE == 1) vreg[i] = idx < M ? vsrc[addr[i]] : 0u;
       if constexpr (VMODE == 2) vreg[i] = runid[i];
@@ -1497,7 +1505,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
           const uint32_t j0 = 2 * w * tid < F ? 2 * w * tid : F;
           const uint32_t j1 = 2 * w * tid + 2 * w < F ? 2 * w * tid + 2 * w : F;
           const uint32_t a0 = off_at(j0), b1 = off_at(j1);
-          const uint32_t cc = tid < np ? (b1 - a0 + kRoundItems - 1) / kRoundItems : 0u;
+          const uint32_t cc = tid < np ? (b1 - a0 + CI - 1) / CI : 0u;
           uint32_t xc = cc;
 #pragma unroll
           for (int d = 1; d < 64; d <<= 1) {
@@ -1510,8 +1518,8 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
       }
     }
 #pragma unroll
-    for (int i = 0; i < kMergeItems; ++i) {
-      const uint32_t idx = i * kMergeThreads + tid;
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint32_t idx = i * NT + tid;
       if (idx < M) {
         sk[lpos[i]] = kreg[i];
         if constexpr (KV) sv[lpos[i]] = vreg[i];
@@ -1519,7 +1527,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
     }
     if constexpr (GAPS) {
       // the gap after segment b: slots soff[b+1] + b*G .. + G
-      for (uint32_t t = tid; t < F * G; t += kMergeThreads) {
+      for (uint32_t t = tid; t < F * G; t += NT) {
         const uint32_t b = t / G;
         sk[soff[b + 1] + b * G + (t - b * G)] = key_max<U>();
       }
@@ -1530,16 +1538,15 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
   // rounds of pairwise stable merges: at width w, runs of w consecutive
   // segments are merged in pairs (the lower run wins ties)
   if constexpr (MAXF <= 64) {
-    // Each pair's output is cut into chunks of kRoundItems that never cross
-    // into the next pair; a chunk prefix over pairs maps threads to chunks.
-    // With at most 32 pairs, M <= kPart keys fit in kMergeThreads chunks.
-    constexpr int CI = kRoundItems;
+    // Each pair's output is cut into chunks of CI that never cross into the
+    // next pair; a chunk prefix over pairs maps threads to chunks.  With at
+    // most 32 pairs, M <= kPart keys fit in NT chunks.
     uint32_t round = 0;
     for (uint32_t w = 1; w < F; w <<= 1, ++round) {
       const uint32_t npairs = (F + 2 * w - 1) / (2 * w);
       const uint32_t *cp = cpre + round * 33;
       const uint32_t nchunks = cp[npairs];
-      if (nchunks > kMergeThreads && tid == 0) report(kErrPartSize);  // cannot happen for M <= kPart
+      if (nchunks > NT && tid == 0) report(kErrPartSize);  // cannot happen for M <= kPart
       U rk[CI];
       uint32_t rv[KV ? CI : 1];
       uint32_t start = 0, count = 0, gap_at = 0;
@@ -1601,10 +1608,10 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
       __syncthreads();
     }
   } else {
-  const uint32_t p0 = tid * kMergeItems;
+  const uint32_t p0 = tid * ITEMS;
   for (uint32_t w = 1; w < F; w <<= 1) {
-    U rk[kMergeItems];
-    uint32_t rv[KV ? kMergeItems : 1];
+    U rk[ITEMS];
+    uint32_t rv[KV ? ITEMS : 1];
     if (p0 < M) {
       uint32_t A0 = 0, A1 = 0, B1 = 0, ai = 0, bi = 0, la = 0, lb = 0;
       U ka = 0, kb = 0;
@@ -1639,7 +1646,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
       };
       locate(p0);
 #pragma unroll
-      for (int i = 0; i < kMergeItems; ++i) {
+      for (int i = 0; i < ITEMS; ++i) {
         if (p0 + i < M) {
           if (A0 + ai + bi == B1) locate(p0 + i);
           const bool takeA = ai < la && (bi >= lb || ka <= kb);
@@ -1663,7 +1670,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
     __syncthreads();
     if (p0 < M) {
 #pragma unroll
-      for (int i = 0; i < kMergeItems; ++i) {
+      for (int i = 0; i < ITEMS; ++i) {
         if (p0 + i < M) {
           sk[p0 + i] = rk[i];
           if constexpr (KV) sv[p0 + i] = rv[i];
@@ -1675,8 +1682,8 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
   }
 
 #pragma unroll
-  for (int i = 0; i < kMergeItems; ++i) {
-    const uint32_t idx = i * kMergeThreads + tid;
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t idx = i * NT + tid;
     if (idx < M) {
       const U k = sk[idx];
       dst[pi.out_off + idx] = final_pass ? Key<KT>::unmap(k) : k;
@@ -1694,19 +1701,19 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(
       const uint64_t seg = gi / g.groups_per_seg, gg = gi % g.groups_per_seg;
       sbase = seg * (g.seg_len >> kSampleLog2) + ((gg * g.group_len + rlo) >> kSampleLog2);
     }
-    for (uint32_t i = tid; i < (M >> kSampleLog2); i += kMergeThreads)
+    for (uint32_t i = tid; i < (M >> kSampleLog2); i += NT)
       samples[sbase + i] = sk[(i << kSampleLog2) + kSample - 1];
   }
   if constexpr (VMODE == 2) {
     // per-run prefix counts at every kChunk-th output of this partition
     const uint32_t nch = (M + kChunk - 1) / kChunk;
-    for (uint32_t i = tid; i < nch * F; i += kMergeThreads) hist[i] = 0;
+    for (uint32_t i = tid; i < nch * F; i += NT) hist[i] = 0;
     __syncthreads();
-    for (uint32_t i = tid; i < M; i += kMergeThreads)
+    for (uint32_t i = tid; i < M; i += NT)
       atomicAdd(&hist[(i / kChunk) * F + sv[i]], 1u);
     __syncthreads();
     const uint64_t prow0 = (uint64_t)blockIdx.x * (kPart / kChunk);
-    for (uint32_t b = tid; b < F; b += kMergeThreads) {
+    for (uint32_t b = tid; b < F; b += NT) {
       uint32_t run = pi.lo_row[b];
       for (uint32_t c = 0; c < nch; ++c) {
         prefix[(prow0 + c) * g.fan + b] = run;
@@ -2093,7 +2100,8 @@ hipError_t launch_merge(int kt, int vmode, const void *src, const uint32_t *vsrc
       using U = decltype(u);
       constexpr int KTI = sizeof(U) == 8 ? 2 : 0;
       MergeBufs<U> b{(const U *)src, (const U *)src, vsrc, vsrc, (U *)dst, (U *)dst, vdst, vdst};
-      hipLaunchKernelGGL((merge_kernel<KTI, 2, 64>), dim3((uint32_t)parts), dim3(kMergeThreads), 0, s,
+      hipLaunchKernelGGL((merge_kernel<KTI, 2, 64, 2 * kMergeThreads>), dim3((uint32_t)parts),
+                         dim3(2 * kMergeThreads), 0, s,
                          b, g, table, part_offsets, 0, (U *)nullptr, prefix);
       return hipGetLastError();
     };
@@ -2112,7 +2120,10 @@ hipError_t launch_merge(int kt, int vmode, const void *src, const uint32_t *vsrc
     auto go = [&](auto vm, auto maxf) -> hipError_t {
       constexpr int VM = decltype(vm)::value;
       constexpr uint32_t MAXF = decltype(maxf)::value;
-      hipLaunchKernelGGL((merge_kernel<KT, VM, MAXF>), dim3((uint32_t)parts), dim3(kMergeThreads), 0, s,
+      // key-value merges hold 12 bytes a key in LDS (one workgroup per CU):
+      // twice the threads there hide more latency
+      constexpr uint32_t NT = VM == 1 && MAXF <= 64 ? 2 * kMergeThreads : kMergeThreads;
+      hipLaunchKernelGGL((merge_kernel<KT, VM, MAXF, NT>), dim3((uint32_t)parts), dim3(NT), 0, s,
                          b, g, table, part_offsets, final_pass, (U *)samples, (uint32_t *)nullptr);
       return hipGetLastError();
     };

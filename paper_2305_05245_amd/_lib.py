@@ -11,7 +11,8 @@ import os
 import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpss.so")
+# PSS_LIB may name another build of the library (e.g. to compare two builds)
+LIB_PATH = os.environ.get("PSS_LIB") or os.path.join(HERE, "libpss.so")
 
 # pss_key_t
 U32, I32, U64, I64, F32, F64 = 0, 1, 2, 3, 4, 5

@@ -1329,7 +1329,7 @@ template <typename U> struct MergeBufs {
 };
 
 template <int KT, int VMODE, uint32_t MAXF, uint32_t NT = kMergeThreads>
-__global__ __launch_bounds__(NT) void merge_kernel(
+__global__ __launch_bounds__(NT, (VMODE == 0 && NT > kMergeThreads) ? 2 : 1) void merge_kernel(
     MergeBufs<typename Key<KT>::U> bufs, RunGeom g, const uint32_t *__restrict__ table,
     const uint64_t *__restrict__ part_off, int final_pass,
     typename Key<KT>::U *__restrict__ samples, uint32_t *__restrict__ prefix) {
@@ -2128,8 +2128,12 @@ hipError_t launch_merge(int kt, int vmode, const void *src, const uint32_t *vsrc
       return hipGetLastError();
     };
     const bool kv = vmode == 1;
-    if (!kv && g.fan <= 32)
-      return go(std::integral_constant<int, 0>{}, std::integral_constant<uint32_t, 32>{});
+    if (!kv && g.fan <= 32) {
+      constexpr uint32_t NT = 2 * kMergeThreads;
+      hipLaunchKernelGGL((merge_kernel<KT, 0, 32, NT>), dim3((uint32_t)parts), dim3(NT), 0, s,
+                         b, g, table, part_offsets, final_pass, (U *)samples, (uint32_t *)nullptr);
+      return hipGetLastError();
+    }
     if (g.fan <= 64)
       return kv ? go(std::integral_constant<int, 1>{}, std::integral_constant<uint32_t, 64>{})
                 : go(std::integral_constant<int, 0>{}, std::integral_constant<uint32_t, 64>{});

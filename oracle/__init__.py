@@ -2,7 +2,8 @@
 
 A plain, sequential CPU implementation of the paper's four-step parallel
 samplesort with exact splitting (PSES; arXiv 2305.05245, Section 2, Section 2.3
-Eq. 1 and Eq. 2), written in C (``pses_oracle.c``) and wrapped here with ctypes
+Eq. 1 and Eq. 2), and of the same steps with regular-sampling pivots (PSRS,
+Section 2.3), written in C (``pses_oracle.c``) and wrapped here with ctypes
 and numpy.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
 of ``bench.py`` may import this package; the GPU library never does.
 
@@ -74,6 +75,9 @@ def bind(path: str):
     lib.oracle_pses.argtypes = [ctypes.c_int, u64, vp, vp, u32, u32, vp, vp,
                                 vp, vp, vp, vp, vp, ctypes.c_int]
     lib.oracle_pses.restype = ctypes.c_int
+    lib.oracle_psrs.argtypes = [ctypes.c_int, u64, vp, vp, u32, u32, vp, vp,
+                                vp, vp, vp, vp, vp, vp]
+    lib.oracle_psrs.restype = ctypes.c_int
     lib.oracle_rank_counts.argtypes = [ctypes.c_int, u64, vp, u64, vp, vp]
     lib.oracle_rank_counts.restype = None
     return lib
@@ -143,6 +147,52 @@ def pses(keys: np.ndarray, n_blocks: int, n_parts: int, vals: np.ndarray | None 
     if rc != 0:
         raise RuntimeError(f"oracle_pses failed: {ERRORS.get(rc, rc)}")
     return PsesResult(out, vout, blocks, pivots, counts, split, offsets)
+
+
+@dataclass
+class PsrsResult:
+    keys: np.ndarray          # sorted output
+    vals: np.ndarray | None   # payload in output order (stable by input index)
+    blocks: np.ndarray        # step 1: concatenation of the sorted blocks
+    samples: np.ndarray       # step 2: the sorted regular samples S
+    pivots: np.ndarray        # step 2: P_1..P_{n_P-1} (raw key dtype)
+    split: np.ndarray         # step 3: [n_B, n_P+1] uint64 boundaries
+    offsets: np.ndarray       # step 4: O_0..O_{n_P} (uint64), O_k = |{x <= P_k}|
+
+    @property
+    def sizes(self) -> np.ndarray:
+        return np.diff(self.offsets.astype(np.int64))
+
+
+def psrs(keys: np.ndarray, n_blocks: int, n_parts: int, vals: np.ndarray | None = None,
+         lib=None) -> PsrsResult:
+    """The four steps with PSRS (regular-sampling) pivots on host arrays."""
+    keys = np.ascontiguousarray(keys)
+    name = {np.dtype(v[1]): k for k, v in DTYPES.items()}[keys.dtype]
+    code = dtype_code(name)
+    n = keys.size
+    out = np.empty_like(keys)
+    blocks = np.empty_like(keys)
+    samples = np.zeros(max(n_blocks * (n_parts - 1), 1), dtype=keys.dtype)
+    ns = ctypes.c_uint64()
+    pivots = np.zeros(max(n_parts - 1, 0), dtype=keys.dtype)
+    split = np.zeros((n_blocks, n_parts + 1), dtype=np.uint64)
+    offsets = np.zeros(n_parts + 1, dtype=np.uint64)
+    vin = vout = None
+    if vals is not None:
+        vin = np.ascontiguousarray(vals, dtype=np.uint32)
+        assert vin.size == n
+        vout = np.empty_like(vin)
+
+    def p(a):
+        return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+    rc = (lib or _load()).oracle_psrs(code, n, p(keys), p(vin), n_blocks, n_parts, p(out), p(vout),
+                                      p(blocks), p(samples), ctypes.byref(ns),
+                                      p(pivots) if pivots.size else None, p(split), p(offsets))
+    if rc != 0:
+        raise RuntimeError(f"oracle_psrs failed: {ERRORS.get(rc, rc)}")
+    return PsrsResult(out, vout, blocks, samples[:ns.value].copy(), pivots, split, offsets)
 
 
 def rank_counts(keys: np.ndarray, v, lib=None) -> tuple[int, int]:

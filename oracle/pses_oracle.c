@@ -14,6 +14,8 @@
  *   O4  offsets of the merged partitions, computed sequentially (Section 2)
  *   O5  step 4: multiway merge of the k-th partition of every block with a
  *       selection tree (Section 2.2, tree selection after Knuth vol. 3)
+ * and, for comparison, the same steps with PSRS pivots (regular sampling,
+ * Section 2.3, first paragraph; oracle_psrs at the end of this file).
  * Everything is done one element at a time, in the order the paper states the
  * steps, with no blocking or fusion.  Slow on purpose.
  */
@@ -420,4 +422,126 @@ void oracle_rank_counts(int dtype, uint64_t n, const void *keys, uint64_t v,
   }
   *lt = a;
   *le = b;
+}
+
+/* ------------------------------------------ PSRS pivots (Section 2.3) ---- */
+
+/* The same four steps with the pivots of parallel sorting by regular sampling
+ * (Section 2.3, first paragraph): n_P - 1 samples are taken at regular
+ * intervals from every sorted block, all samples are sorted, n_P - 1 pivots
+ * are taken at regular intervals from the sorted samples, and every block is
+ * partitioned by value alone (partition k: P_k < x <= P_{k+1}, Section 2), so
+ * partition sizes follow the data.  Regular intervals are read as the
+ * positions floor(j len / n_P), j = 1..n_P-1, of a sorted sequence of length
+ * len, both inside a block and in the sorted samples (P_k = S[floor(k |S| /
+ * n_P)]); an empty block gives no samples. */
+int oracle_psrs(int dtype, uint64_t n, const void *keys, const uint32_t *vals,
+                uint32_t n_b, uint32_t n_p, void *keys_out, uint32_t *vals_out,
+                void *blocks_out, void *samples_out, uint64_t *n_samples,
+                void *pivots, uint64_t *split, uint64_t *offsets) {
+  const int kb = key_bytes(dtype);
+  if (!kb || n_b == 0 || n_p == 0 || (n && (!keys || !keys_out))) return ORACLE_ERR_ARGS;
+  if (vals && n && !vals_out) return ORACLE_ERR_ARGS;
+
+  int rc = ORACLE_OK;
+  const uint64_t per = n_p - 1;
+  elem_t *all = (elem_t *)malloc((n ? n : 1) * sizeof(elem_t));
+  elem_t **blk = (elem_t **)malloc(n_b * sizeof(elem_t *));
+  uint64_t *blen = (uint64_t *)malloc(n_b * sizeof(uint64_t));
+  elem_t *smp = (elem_t *)malloc(((size_t)n_b * per + 1) * sizeof(elem_t));
+  uint64_t *piv = (uint64_t *)calloc(n_p, sizeof(uint64_t));
+  uint64_t *s = (uint64_t *)malloc((size_t)n_b * (n_p + 1) * sizeof(uint64_t));
+  uint64_t *off = (uint64_t *)malloc((n_p + 1) * sizeof(uint64_t));
+  const elem_t **seg = (const elem_t **)malloc(n_b * sizeof(elem_t *));
+  uint64_t *seg_len = (uint64_t *)malloc(n_b * sizeof(uint64_t));
+  elem_t *merged = (elem_t *)malloc((n ? n : 1) * sizeof(elem_t));
+  uint64_t ns = 0;
+  if (!all || !blk || !blen || !smp || !piv || !s || !off || !seg || !seg_len || !merged) {
+    rc = ORACLE_ERR_NOMEM;
+    goto done;
+  }
+
+  /* Step 1: blocks of ceil(N/n_B) elements, each sorted on its own. */
+  for (uint64_t i = 0; i < n; ++i) {
+    all[i].bits = load_bits(keys, i, kb);
+    all[i].idx = i;
+    all[i].val = vals ? vals[i] : 0;
+  }
+  for (uint32_t b = 0; b < n_b; ++b) {
+    uint64_t lo, hi;
+    block_range(n, n_b, b, &lo, &hi);
+    blk[b] = all + lo;
+    blen[b] = hi - lo;
+    rc = merge_sort_stable(dtype, blk[b], blen[b]);
+    if (rc) goto done;
+  }
+  if (blocks_out)
+    for (uint64_t i = 0; i < n; ++i) store_bits(blocks_out, i, kb, all[i].bits);
+
+  /* Step 2: regular samples of every non-empty block, sorted; pivots at
+   * regular intervals of the sorted samples. */
+  for (uint32_t b = 0; b < n_b; ++b) {
+    if (blen[b] == 0) continue;
+    for (uint64_t j = 1; j <= per; ++j) smp[ns++] = blk[b][(uint64_t)(((u128)j * blen[b]) / n_p)];
+  }
+  rc = merge_sort_stable(dtype, smp, ns);
+  if (rc) goto done;
+  for (uint32_t k = 1; k < n_p; ++k)
+    piv[k] = ns ? smp[(uint64_t)(((u128)k * ns) / n_p)].bits : 0;
+
+  /* Step 3: boundary k of block b after every element <= P_k. */
+  for (uint32_t b = 0; b < n_b; ++b) {
+    s[(size_t)b * (n_p + 1) + 0] = 0;
+    s[(size_t)b * (n_p + 1) + n_p] = blen[b];
+    for (uint32_t k = 1; k < n_p; ++k)
+      s[(size_t)b * (n_p + 1) + k] = ns ? count_less_equal(dtype, blk[b], blen[b], piv[k]) : 0;
+    for (uint32_t k = 0; k < n_p; ++k)
+      if (s[(size_t)b * (n_p + 1) + k] > s[(size_t)b * (n_p + 1) + k + 1]) {
+        rc = ORACLE_ERR_SPLIT_MONO;
+        goto done;
+      }
+  }
+
+  /* Offsets of the merged partitions, one after another; each boundary is the
+   * number of elements <= P_k. */
+  off[0] = 0;
+  for (uint32_t k = 0; k < n_p; ++k) {
+    uint64_t m = 0;
+    for (uint32_t b = 0; b < n_b; ++b)
+      m += s[(size_t)b * (n_p + 1) + k + 1] - s[(size_t)b * (n_p + 1) + k];
+    off[k + 1] = off[k] + m;
+  }
+  for (uint32_t k = 1; k < n_p; ++k)
+    if (ns && off[k] != global_count_le(dtype, blk, blen, n_b, piv[k])) {
+      rc = ORACLE_ERR_SPLIT_SUM;
+      goto done;
+    }
+
+  /* Step 4: merge partition k of every block into merged[O_k ...]. */
+  for (uint32_t k = 0; k < n_p; ++k) {
+    for (uint32_t b = 0; b < n_b; ++b) {
+      const uint64_t a = s[(size_t)b * (n_p + 1) + k], e = s[(size_t)b * (n_p + 1) + k + 1];
+      seg[b] = blk[b] + a;
+      seg_len[b] = e - a;
+    }
+    rc = merge_selection_tree(dtype, seg, seg_len, n_b, merged + off[k]);
+    if (rc) goto done;
+  }
+
+  for (uint64_t i = 0; i < n; ++i) {
+    store_bits(keys_out, i, kb, merged[i].bits);
+    if (vals) vals_out[i] = merged[i].val;
+  }
+  if (samples_out)
+    for (uint64_t i = 0; i < ns; ++i) store_bits(samples_out, i, kb, smp[i].bits);
+  if (n_samples) *n_samples = ns;
+  if (pivots)
+    for (uint32_t k = 1; k < n_p; ++k) store_bits(pivots, k - 1, kb, piv[k]);
+  if (split) memcpy(split, s, (size_t)n_b * (n_p + 1) * sizeof(uint64_t));
+  if (offsets) memcpy(offsets, off, (n_p + 1) * sizeof(uint64_t));
+
+done:
+  free(all); free(blk); free(blen); free(smp); free(piv); free(s); free(off);
+  free(seg); free(seg_len); free(merged);
+  return rc;
 }

@@ -2,7 +2,8 @@
  * pses_oracle.h -- TEST INFRASTRUCTURE ONLY.
  *
  * A plain, sequential, deliberately slow CPU reference of parallel samplesort
- * with exact splitting (PSES), Tokuue & Ishiyama, "Performance Evaluation of
+ * with exact splitting (PSES), and of its regular-sampling variant (PSRS),
+ * Tokuue & Ishiyama, "Performance Evaluation of
  * Parallel Sortings on the Supercomputer Fugaku" (arXiv 2305.05245).
  * It exists so that tests, the smoke check and the benchmark's CPU-baseline leg
  * can check the GPU library against an independent implementation.  The GPU
@@ -65,6 +66,25 @@ int oracle_pses(int dtype, uint64_t n, const void *keys, const uint32_t *vals,
                 uint32_t *vals_out, void *blocks_out, void *pivots,
                 uint64_t *counts, uint64_t *split, uint64_t *offsets,
                 int merge_kind);
+
+/*
+ * The same four steps with the pivots of parallel sorting by regular sampling
+ * (PSRS, Section 2.3, first paragraph): n_P - 1 samples from every non-empty
+ * sorted block at positions floor(j len_b / n_P) (j = 1..n_P-1), the samples
+ * sorted, P_k = S[floor(k |S| / n_P)], and every block cut by value alone
+ * (partition k holds P_k < x <= P_{k+1}), so the sizes follow the data.
+ *
+ *   samples_out         optional: the sorted samples S (up to n_B*(n_P-1)
+ *                       keys; their number is written to *n_samples)
+ *   pivots              optional: n_P-1 keys P_k (0 when there are no samples)
+ *   split, offsets      as for oracle_pses; offsets[k] = |{x <= P_k}|
+ * Other arguments as for oracle_pses (the merge is the selection tree).
+ */
+int oracle_psrs(int dtype, uint64_t n, const void *keys, const uint32_t *vals,
+                uint32_t n_blocks, uint32_t n_parts, void *keys_out,
+                uint32_t *vals_out, void *blocks_out, void *samples_out,
+                uint64_t *n_samples, void *pivots, uint64_t *split,
+                uint64_t *offsets);
 
 /* Plain counts |{x in keys : x < v}| and |{x in keys : x <= v}| by one linear
  * pass: the definition used by Eq. 1, for checks at sizes where the full

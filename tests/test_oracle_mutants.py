@@ -17,6 +17,7 @@ import pytest
 
 import oracle
 import refdefs
+from test_oracle_psrs import check_single_block_closed_form, check_worked_examples
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "pses_oracle.c")
@@ -53,13 +54,45 @@ MUTANTS = {
     "tree replay keeps loser": (
         "    t->node[node] = run_beats(t, r, l) ? r : l;\n  }\n}",
         "    t->node[node] = run_beats(t, l, r) ? r : l;\n  }\n}"),
-    "merge reads segment end as start": ("seg[b] = blk[b] + a;", "seg[b] = blk[b] + (a ? a - 1 : 0);"),
+    "merge reads segment end as start": (
+        "seg[b] = blk[b] + a;\n      seg_len[b] = e - a;\n    }\n    rc = merge_kind",
+        "seg[b] = blk[b] + (a ? a - 1 : 0);\n      seg_len[b] = e - a;\n    }\n    rc = merge_kind"),
+    # PSRS (regular-sampling pivots)
+    "psrs sample positions shifted down": (
+        "smp[ns++] = blk[b][(uint64_t)(((u128)j * blen[b]) / n_p)];",
+        "smp[ns++] = blk[b][(uint64_t)(((u128)(j - 1) * blen[b]) / n_p)];"),
+    "psrs samples left unsorted": ("rc = merge_sort_stable(dtype, smp, ns);", "rc = ORACLE_OK;"),
+    "psrs pivot index divided first": (
+        "piv[k] = ns ? smp[(uint64_t)(((u128)k * ns) / n_p)].bits : 0;",
+        "piv[k] = ns ? smp[(uint64_t)k * (ns / n_p)].bits : 0;"),
+    "psrs partition by lower bound": (
+        "? count_less_equal(dtype, blk[b], blen[b], piv[k]) : 0;",
+        "? count_less(dtype, blk[b], blen[b], piv[k]) : 0;"),
+    "psrs merge tie to higher block": (
+        "rc = merge_selection_tree(dtype, seg, seg_len, n_b, merged + off[k]);\n    if (rc) goto done;\n  }\n\n  for (uint64_t i = 0; i < n; ++i) {\n    store_bits(keys_out, i, kb, merged[i].bits);\n    if (vals) vals_out[i] = merged[i].val;\n  }\n  if (samples_out)",
+        "for (uint32_t h = 0; h < n_b / 2; ++h) { const elem_t *t = seg[h]; seg[h] = seg[n_b - 1 - h]; seg[n_b - 1 - h] = t; uint64_t u = seg_len[h]; seg_len[h] = seg_len[n_b - 1 - h]; seg_len[n_b - 1 - h] = u; }\n    rc = merge_selection_tree(dtype, seg, seg_len, n_b, merged + off[k]);\n    if (rc) goto done;\n  }\n\n  for (uint64_t i = 0; i < n; ++i) {\n    store_bits(keys_out, i, kb, merged[i].bits);\n    if (vals) vals_out[i] = merged[i].val;\n  }\n  if (samples_out)"),
 }
+
+
+def psrs_pins(lib) -> None:
+    """Compact pins of the PSRS variant: hand-worked examples, the one-block
+    closed form, and the stable output with values on duplicate-heavy keys."""
+    check_worked_examples(oracle, lib=lib)
+    rng = np.random.default_rng(4)
+    check_single_block_closed_form(oracle, rng, lib=lib)
+    for _ in range(4):
+        n = int(rng.integers(1, 400))
+        keys = rng.integers(0, 5, size=n).astype(np.int64)
+        vals = np.arange(n, dtype=np.uint32)
+        r = oracle.psrs(keys, int(rng.integers(2, 20)), int(rng.integers(2, 20)), vals=vals, lib=lib)
+        perm = refdefs.stable_order(keys)
+        assert np.array_equal(r.keys, keys[perm]) and np.array_equal(r.vals, perm)
 
 
 def pin_suite(lib) -> None:
     """Compact pins: worked examples, totalOrder table, brute force, closed
     forms and random inputs.  Raises on the first failed pin."""
+    psrs_pins(lib)
     with open(os.path.join(GOLDEN, "fig1_parallel_sort.json")) as f:
         g1 = json.load(f)
     r = oracle.pses(np.array(g1["keys"], dtype=np.uint32), 2, 2, lib=lib)

@@ -161,6 +161,46 @@ pss_status pss_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, uint6
                          size_t ws_bytes, void *stream);
 
 /*
+ * The paper's single level with the pivots of parallel sorting by regular
+ * sampling (PSRS, Section 2.3, first paragraph) instead of exact splitting,
+ * for comparison: step 1 as in pss_sort with n_blocks, n_parts > 0; step 2
+ * takes n_P - 1 samples from every non-empty sorted block at its positions
+ * floor(j len_b / n_P), j = 1..n_P-1, sorts the samples (S, n_s = non-empty
+ * blocks * (n_P - 1) keys; non-empty blocks = ceil(n / ceil(n / n_B))), and
+ * takes P_k = S[floor(k n_s / n_P)]; step 3 cuts every block by value alone,
+ * partition k holding the keys P_k < x <= P_{k+1} (Section 2), so partition
+ * sizes follow the data (on Duplicate3-like inputs at most three partitions
+ * are non-empty, Fig. 3a); step 4 merges partition k of every block into the
+ * output at offset |{x <= P_k}|, cut into chunks of at most 8192 keys.  The
+ * output is the same stable sort as pss_sort's.
+ *   part_sizes: optional DEVICE array of n_P uint64 partition sizes.
+ * Limits: at most 2^27 samples.  Workspace: pss_psrs_workspace_bytes.  Other
+ * arguments, ownership and errors as for pss_sort.
+ */
+pss_status pss_psrs_workspace_bytes(const pss_ctx *ctx, pss_key_t key, pss_val_t val, uint64_t n,
+                                    uint32_t n_blocks, uint32_t n_parts, size_t *bytes);
+pss_status pss_psrs_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys_in,
+                         void *keys_out, const uint32_t *vals_in, uint32_t *vals_out, uint64_t n,
+                         uint32_t n_blocks, uint32_t n_parts, uint64_t *part_sizes, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/*
+ * Steps 1-3 of the PSRS variant (see pss_psrs_sort), for inspection and
+ * parity checks.  Any output may be NULL (all DEVICE arrays):
+ *   sorted_blocks: n keys, the sorted blocks (step 1).
+ *   samples: n_s keys, the sorted regular samples S.
+ *   pivots: n_P - 1 keys P_k.
+ *   split: n_B * (n_P + 1) values, row-major [b][k]: the number of keys
+ *     <= P_k in sorted block b (column 0 is 0, column n_P the block length).
+ *   offsets: n_P + 1 values, offsets[k] = |{x <= P_k}| (0 and n at the ends).
+ * Workspace as for pss_psrs_sort with the same arguments.
+ */
+pss_status pss_psrs_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, uint64_t n,
+                              uint32_t n_blocks, uint32_t n_parts, void *sorted_blocks,
+                              void *samples, void *pivots, uint64_t *split, uint64_t *offsets,
+                              void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Batched segmented sort: sort each segment [seg_offsets[i], seg_offsets[i+1])
  * of one array independently (ascending; key-value sorts stable within the
  * segment), all segments in one fixed sequence of launches with no host round

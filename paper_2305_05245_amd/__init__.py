@@ -8,6 +8,7 @@ current HIP stream; every step of the sort runs in the library's HIP kernels.
     out, vals = pss.sort(keys, vals)             # stable key-value sort
     out, _ = pss.sort(keys, n_blocks=64, n_parts=64)   # the paper's single level
     info = pss.splitters(keys, 64, 64)           # steps 1-3 (pivots, c_k, split)
+    out, _, sizes = pss.psrs_sort(keys, n_blocks=64, n_parts=64)  # regular-sampling pivots
 """
 from __future__ import annotations
 
@@ -18,7 +19,7 @@ import torch
 from . import _lib
 from ._lib import PssError, Tuning, plan, validate, workspace_bytes  # noqa: F401
 
-__all__ = ["sort", "segmented_sort", "splitters", "device_check", "Tuning", "key_type_of", "plan", "workspace_bytes", "PssError",
+__all__ = ["sort", "segmented_sort", "splitters", "psrs_sort", "psrs_splitters", "device_check", "Tuning", "key_type_of", "plan", "workspace_bytes", "PssError",
            "Workspace"]
 
 _DTYPE_KEY = {
@@ -215,4 +216,67 @@ def splitters(keys: torch.Tensor, n_blocks: int, n_parts: int,
     ctx.splitters(kt, keys.data_ptr(), n, n_blocks, n_parts, ptr(res["sorted_blocks"]),
                   ptr(res["pivots"]), ptr(res["counts"]), ptr(res["split"]), ptr(res["offsets"]),
                   ws.data_ptr(), ws.numel(), _stream_handle(dev))
+    return res
+
+
+def psrs_sort(keys: torch.Tensor, vals: torch.Tensor | None = None, n_blocks: int = 64,
+              n_parts: int = 64, key_type: str | int | None = None,
+              out: torch.Tensor | None = None, vals_out: torch.Tensor | None = None):
+    """The paper's single level with regular-sampling (PSRS) pivots instead of
+    exact splitting: same output as `sort`, partition sizes that follow the
+    data.  Returns (sorted_keys, sorted_vals or None, partition_sizes [n_P]
+    int64 device tensor)."""
+    if not keys.is_cuda or keys.dim() != 1 or not keys.is_contiguous():
+        raise ValueError("keys must be a contiguous 1-D device tensor")
+    kt = key_type_of(keys, key_type)
+    if keys.element_size() != _lib.KEY_BYTES[kt]:
+        raise ValueError("key dtype width does not match key_type")
+    dev = keys.device.index if keys.device.index is not None else torch.cuda.current_device()
+    n = keys.numel()
+    vt = _lib.VAL_NONE
+    if vals is not None:
+        if not vals.is_cuda or vals.numel() != n or vals.element_size() != 4 or not vals.is_contiguous():
+            raise ValueError("vals must be a contiguous device tensor of n 4-byte elements")
+        vt = _lib.VAL_U32
+    if out is None:
+        out = torch.empty_like(keys)
+    if vals is not None and vals_out is None:
+        vals_out = torch.empty_like(vals)
+    sizes = torch.empty(n_parts, dtype=torch.int64, device=keys.device)
+    ws = Workspace.get(dev, _lib.psrs_workspace_bytes(kt, vt, n, n_blocks, n_parts))
+    _context(dev).psrs_sort(kt, vt, keys.data_ptr(), out.data_ptr(),
+                            vals.data_ptr() if vals is not None else 0,
+                            vals_out.data_ptr() if vals is not None else 0, n, n_blocks, n_parts,
+                            sizes.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(dev))
+    return out, (vals_out if vals is not None else None), sizes
+
+
+def psrs_splitters(keys: torch.Tensor, n_blocks: int, n_parts: int,
+                   key_type: str | int | None = None) -> dict:
+    """Steps 1-3 with regular-sampling pivots on the device: sorted blocks,
+    sorted samples S, pivots P_k = S[floor(k |S| / n_P)], the split table
+    [n_B, n_P+1] (keys <= P_k per block) and offsets |{x <= P_k}|."""
+    if not keys.is_cuda or keys.dim() != 1 or not keys.is_contiguous():
+        raise ValueError("keys must be a contiguous 1-D device tensor")
+    kt = key_type_of(keys, key_type)
+    dev = keys.device.index if keys.device.index is not None else torch.cuda.current_device()
+    n = keys.numel()
+    d = keys.device
+    res = {
+        "sorted_blocks": torch.empty_like(keys),
+        "samples": torch.empty(_lib.psrs_sample_count(n, n_blocks, n_parts), dtype=keys.dtype,
+                               device=d),
+        "pivots": torch.zeros(max(n_parts - 1, 0), dtype=keys.dtype, device=d),
+        "split": torch.zeros((n_blocks, n_parts + 1), dtype=torch.int64, device=d),
+        "offsets": torch.zeros(n_parts + 1, dtype=torch.int64, device=d),
+    }
+    ws = Workspace.get(dev, _lib.psrs_workspace_bytes(kt, _lib.VAL_NONE, n, n_blocks, n_parts))
+
+    def ptr(t):
+        return t.data_ptr() if t.numel() else 0
+
+    _context(dev).psrs_splitters(kt, keys.data_ptr(), n, n_blocks, n_parts,
+                                 ptr(res["sorted_blocks"]), ptr(res["samples"]),
+                                 ptr(res["pivots"]), ptr(res["split"]), ptr(res["offsets"]),
+                                 ws.data_ptr(), ws.numel(), _stream_handle(dev))
     return res

@@ -80,6 +80,11 @@ SIGNATURES = {
     "pss_server_destroy": (None, [_vp]),
     "pss_splitters": (_int, [_vp, _int, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                              _vp]),
+    "pss_psrs_workspace_bytes": (_int, [_vp, _int, _int, _u64, _u32, _u32, _c.POINTER(_sz)]),
+    "pss_psrs_sort": (_int, [_vp, _int, _int, _vp, _vp, _vp, _vp, _u64, _u32, _u32, _vp, _vp, _sz,
+                             _vp]),
+    "pss_psrs_splitters": (_int, [_vp, _int, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                  _sz, _vp]),
 }
 
 _lock = threading.Lock()
@@ -135,6 +140,21 @@ def workspace_bytes(key: int, val: int, n: int, n_blocks: int = 0, n_parts: int 
     out = ctypes.c_size_t()
     check(load().pss_workspace_bytes(None, key, val, n, n_blocks, n_parts, ctypes.byref(out)))
     return int(out.value)
+
+
+def psrs_workspace_bytes(key: int, val: int, n: int, n_blocks: int, n_parts: int) -> int:
+    out = ctypes.c_size_t()
+    check(load().pss_psrs_workspace_bytes(None, key, val, n, n_blocks, n_parts, ctypes.byref(out)))
+    return int(out.value)
+
+
+def psrs_sample_count(n: int, n_blocks: int, n_parts: int) -> int:
+    """Number of regular samples of the PSRS variant: n_P - 1 from each
+    non-empty block of ceil(n / n_B) keys."""
+    if n == 0 or n_parts < 2:
+        return 0
+    L = -(-n // n_blocks)
+    return -(-n // L) * (n_parts - 1)
 
 
 def plan(key: int, val: int, n: int, n_blocks: int = 0, n_parts: int = 0) -> dict:
@@ -245,6 +265,22 @@ class Context:
         code = ctypes.c_uint32()
         check(self.lib.pss_device_check(self.handle, ctypes.byref(code)), self.handle)
         return int(code.value)
+
+    def psrs_sort(self, key: int, val: int, keys_in: int, keys_out: int, vals_in: int,
+                  vals_out: int, n: int, n_blocks: int, n_parts: int, part_sizes: int, ws: int,
+                  ws_bytes: int, stream: int) -> None:
+        check(self.lib.pss_psrs_sort(self.handle, key, val, keys_in or None, keys_out or None,
+                                     vals_in or None, vals_out or None, n, n_blocks, n_parts,
+                                     part_sizes or None, ws or None, ws_bytes, stream or None),
+              self.handle)
+
+    def psrs_splitters(self, key: int, keys_in: int, n: int, n_blocks: int, n_parts: int,
+                       sorted_blocks: int, samples: int, pivots: int, split: int, offsets: int,
+                       ws: int, ws_bytes: int, stream: int) -> None:
+        check(self.lib.pss_psrs_splitters(self.handle, key, keys_in or None, n, n_blocks, n_parts,
+                                          sorted_blocks or None, samples or None, pivots or None,
+                                          split or None, offsets or None, ws or None, ws_bytes,
+                                          stream or None), self.handle)
 
     def splitters(self, key: int, keys_in: int, n: int, n_blocks: int, n_parts: int,
                   sorted_blocks: int, pivots: int, counts: int, split: int, offsets: int,

@@ -307,6 +307,193 @@ pss_status run_segment_sort(pss_ctx *ctx, const Plan &p, int kt, const void *key
   return PSS_OK;
 }
 
+// Automatic-plan sort of p.n keys (and values) from keys_in into keys_out:
+// tile sort and merge passes alternate between keys_out and the workspace so
+// that the last pass lands in keys_out.
+pss_status run_auto_sort(pss_ctx *ctx, const Plan &p, int kt, const void *keys_in,
+                         const uint32_t *vals_in, void *keys_out, uint32_t *vals_out, char *w,
+                         hipStream_t s) {
+  const size_t P = p.passes.size();
+  std::vector<void *> kb(P + 1);
+  std::vector<uint32_t *> vb(P + 1, nullptr);
+  for (size_t q = 0; q <= P; ++q) {
+    const bool to_out = ((P - q) % 2) == 0;
+    kb[q] = to_out ? keys_out : (void *)(w + p.off_keys0);
+    if (p.kv) vb[q] = to_out ? vals_out : (uint32_t *)(w + p.off_vals0);
+  }
+  return run_segment_sort(ctx, p, kt, keys_in, vals_in, kb.data(), vb.data(), 1, w, s);
+}
+
+// Regular-sampling (PSRS) variant of the paper's single level: the same block
+// sort, then n_P - 1 regular samples per block, their sort (an automatic-plan
+// sort of the mapped keys as unsigned integers), pivots at regular intervals
+// of the sorted samples and a value partition of every block, whose sizes
+// follow the data.  Each partition is merged in chunks of at most kPart keys,
+// cut by co-rank rows at the chunk boundaries.
+constexpr uint64_t kMaxPsrsSamples = (uint64_t)1 << 27;
+
+struct PsrsPlan {
+  Plan base;           // paper-mode plan: block sort and workspace buffers
+  Plan smp;            // automatic plan of the sample sort
+  pss::RunGeom top{};  // merge geometry with data-dependent partitions
+  uint64_t ns = 0;     // number of samples
+  int skt = 0;         // key type the samples are sorted as
+  size_t off_table = 0, off_samples = 0, off_ssorted = 0, off_sws = 0;
+  size_t off_bounds = 0, off_chunks = 0, off_cprefix = 0, total = 0;
+};
+
+pss_status make_psrs_plan(pss_key_t key, pss_val_t val, uint64_t n, uint32_t n_blocks,
+                          uint32_t n_parts, PsrsPlan *pp, std::string *err) {
+  pss_status st = make_plan(key, val, n, n_blocks, n_parts, &pp->base, err);
+  if (st != PSS_OK) return st;
+  const uint64_t L = pp->base.seg_len;
+  pp->ns = (n && n_parts > 1) ? ceil_div(n, L) * (uint64_t)(n_parts - 1) : 0;
+  if (pp->ns > kMaxPsrsSamples) {
+    *err = "more than 2^27 regular samples (non-empty blocks * (n_parts - 1))";
+    return PSS_ERR_UNSUPPORTED;
+  }
+  pss::RunGeom &t = pp->top;
+  t = pp->base.top;
+  t.sub_per_part = 1;
+  t.chunk_bound = ceil_div(n, pss::kPart) + n_parts;
+  const uint64_t entries = (t.chunk_bound + 1) * (uint64_t)t.fan;
+  if (entries > kMaxTableEntries) {
+    *err = "n_blocks * (n / 8192 + n_parts) too large for the split table of this build";
+    return PSS_ERR_UNSUPPORTED;
+  }
+  pp->skt = pss::key_bytes((int)key) == 8 ? PSS_U64 : PSS_U32;
+  if (pp->ns) {
+    st = make_plan((pss_key_t)pp->skt, PSS_VAL_NONE, pp->ns, 0, 0, &pp->smp, err);
+    if (st != PSS_OK) return st;
+  }
+  const size_t kb = (size_t)pss::key_bytes((int)key);
+  size_t off = pp->base.total;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  pp->off_table = take(entries * sizeof(uint32_t));
+  pp->off_samples = take(pp->ns * kb);
+  pp->off_ssorted = take(pp->ns * kb);
+  pp->off_sws = take(pp->ns ? pp->smp.total : 0);
+  pp->off_bounds = take(((size_t)n_parts + 1) * sizeof(uint64_t));
+  pp->off_chunks = take((size_t)n_parts * sizeof(uint64_t));
+  pp->off_cprefix = take(((size_t)n_parts + 1) * sizeof(uint64_t));
+  pp->total = off;
+  return PSS_OK;
+}
+
+// Outputs of the PSRS steps (device pointers, each optional).
+struct PsrsOut {
+  void *sorted_blocks = nullptr;
+  void *samples = nullptr;
+  void *pivots = nullptr;
+  uint64_t *split = nullptr;
+  uint64_t *offsets = nullptr;
+  uint64_t *sizes = nullptr;
+};
+
+// Steps 1-3 with regular-sampling pivots, then (merge = true) step 4 into
+// keys_out / vals_out.
+pss_status run_psrs(pss_ctx *ctx, const PsrsPlan &pp, int kt, const void *keys_in,
+                    const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
+                    const PsrsOut &o, bool merge, char *w, hipStream_t s) {
+  const Plan &p = pp.base;
+  const size_t P = p.passes.size();
+  std::vector<void *> kbuf(P + 1);
+  std::vector<uint32_t *> vbuf(P + 1, nullptr);
+  for (size_t q = 0; q <= P; ++q) {
+    const bool even = ((P - q) % 2) == 0;
+    kbuf[q] = even ? (void *)(w + p.off_keys0) : (void *)(w + p.off_keys1);
+    if (p.kv) vbuf[q] = even ? (uint32_t *)(w + p.off_vals0) : (uint32_t *)(w + p.off_vals1);
+  }
+  pss_status st = run_segment_sort(ctx, p, kt, keys_in, vals_in, kbuf.data(), vbuf.data(), 0, w, s);
+  if (st != PSS_OK) return st;
+  const void *blocks = kbuf[P];
+  const size_t kbytes = (size_t)p.kb;
+  void *samples = w + pp.off_samples;
+  void *ssorted = w + pp.off_ssorted;
+  uint64_t *bounds = (uint64_t *)(w + pp.off_bounds);
+  uint64_t *chunks = (uint64_t *)(w + pp.off_chunks);
+  uint64_t *cprefix = (uint64_t *)(w + pp.off_cprefix);
+  if (pp.ns) {
+    {
+      LaunchTimer t(ctx, "psrs_samples", pp.ns * kbytes * 2, s);
+      PSS_TRY(pss::launch_psrs_samples(kt, blocks, pp.top, samples, s), "sample launch");
+    }
+    {
+      // one timing record for the whole sample sort
+      LaunchTimer t(ctx, "psrs_sample_sort", pp.ns * kbytes * 2, s);
+      const bool prof = ctx->profiling;
+      ctx->profiling = false;
+      st = run_auto_sort(ctx, pp.smp, pp.skt, samples, nullptr, ssorted, nullptr,
+                         w + pp.off_sws, s);
+      ctx->profiling = prof;
+      if (st != PSS_OK) return st;
+    }
+    if (o.samples)
+      PSS_TRY(pss::launch_unmap_copy(kt, ssorted, o.samples, pp.ns, s), "sample copy");
+  }
+  {
+    LaunchTimer t(ctx, "psrs_partition", (uint64_t)p.top.fan * (p.top.n_parts + 1) * 8, s);
+    PSS_TRY(pss::launch_psrs_partition(kt, blocks, pp.top, ssorted, pp.ns, bounds, o.pivots,
+                                       o.split, s),
+            "partition launch");
+  }
+  {
+    LaunchTimer t(ctx, "psrs_chunks", (uint64_t)p.top.n_parts * 24, s);
+    PSS_TRY(pss::launch_psrs_chunks(pp.top, bounds, o.sizes, chunks, cprefix, s), "chunk launch");
+  }
+  if (o.offsets)
+    PSS_TRY(hipMemcpyAsync(o.offsets, bounds, ((size_t)p.top.n_parts + 1) * 8,
+                           hipMemcpyDeviceToDevice, s),
+            "offset copy");
+  if (o.sorted_blocks)
+    PSS_TRY(pss::launch_unmap_copy(kt, blocks, o.sorted_blocks, p.n, s), "block copy");
+  if (!merge) return PSS_OK;
+  pss::RunGeom top = pp.top;
+  top.bounds = bounds;
+  top.chunk_prefix = cprefix;
+  uint32_t *table = (uint32_t *)(w + pp.off_table);
+  {
+    LaunchTimer t(ctx, "split_search", top.total_rows() * top.fan * 4, s);
+    PSS_TRY(pss::launch_corank(kt, blocks, top, table, nullptr, nullptr, s), "chunk split launch");
+  }
+  {
+    LaunchTimer t(ctx, "merge", 2 * p.n * ((uint64_t)p.kb + (p.kv ? 4 : 0)), s);
+    PSS_TRY(pss::launch_merge(kt, p.kv ? 1 : 0, blocks, vbuf[P], keys_out, vals_out, top, table,
+                              nullptr, 1, nullptr, nullptr, s),
+            "merge launch");
+  }
+  return PSS_OK;
+}
+
+// Argument checks shared by the two PSRS entry points; fills the plan.
+pss_status psrs_prepare(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys_in,
+                        const void *keys_out, const void *vals_in, const void *vals_out,
+                        uint64_t n, uint32_t n_blocks, uint32_t n_parts, void *ws,
+                        size_t ws_bytes, PsrsPlan *pp) {
+  if (n_blocks == 0 || n_parts == 0)
+    return fail(ctx, PSS_ERR_INVALID, "PSRS needs n_blocks > 0 and n_parts > 0");
+  Plan p;
+  pss_status st = validate(ctx, key, val, keys_in, keys_out, vals_in, vals_out, n, n_blocks,
+                           n_parts, SIZE_MAX, &p);
+  if (st != PSS_OK) return st;
+  if (!ctx) return fail(nullptr, PSS_ERR_INVALID, "null context");
+  std::string err;
+  st = make_psrs_plan(key, val, n, n_blocks, n_parts, pp, &err);
+  if (st != PSS_OK) return fail(ctx, st, err);
+  if (n && ws_bytes < pp->total) {
+    char m[160];
+    snprintf(m, sizeof m, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
+             pp->total);
+    return fail(ctx, PSS_ERR_WORKSPACE, m);
+  }
+  if (n && !ws) return fail(ctx, PSS_ERR_WORKSPACE, "null workspace");
+  return PSS_OK;
+}
+
 }  // namespace
 
 namespace pss {
@@ -478,15 +665,7 @@ pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys
   const size_t P = p.passes.size();
 
   if (!p.paper) {
-    // bufs[P] = output, bufs[P-1] = workspace, alternating backwards
-    std::vector<void *> kb(P + 1);
-    std::vector<uint32_t *> vb(P + 1, nullptr);
-    for (size_t q = 0; q <= P; ++q) {
-      const bool to_out = ((P - q) % 2) == 0;
-      kb[q] = to_out ? keys_out : (void *)(w + p.off_keys0);
-      if (p.kv) vb[q] = to_out ? vals_out : (uint32_t *)(w + p.off_vals0);
-    }
-    st = run_segment_sort(ctx, p, kt, keys_in, vals_in, kb.data(), vb.data(), 1, w, s);
+    st = run_auto_sort(ctx, p, kt, keys_in, vals_in, keys_out, vals_out, w, s);
     if (st != PSS_OK) return st;
   } else {
     // block sort ends in workspace buffer 0; the cross-block merge writes out
@@ -863,6 +1042,72 @@ pss_status pss_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, uint6
   if (split) PSS_TRY(pss::launch_split_table(p.top, table, split, s), "split table launch");
   if (sorted_blocks) PSS_TRY(pss::launch_unmap_copy(kt, kb[P], sorted_blocks, n, s), "block copy");
   return PSS_OK;
+}
+
+pss_status pss_psrs_workspace_bytes(const pss_ctx *ctx, pss_key_t key, pss_val_t val, uint64_t n,
+                                    uint32_t n_blocks, uint32_t n_parts, size_t *bytes) {
+  if (!bytes) return fail(ctx, PSS_ERR_INVALID, "null output pointer");
+  if (n_blocks == 0 || n_parts == 0)
+    return fail(ctx, PSS_ERR_INVALID, "PSRS needs n_blocks > 0 and n_parts > 0");
+  Plan p;
+  const pss_status s = validate(ctx, key, val, nullptr, nullptr, nullptr, nullptr, 0, n_blocks,
+                                n_parts, SIZE_MAX, &p);
+  if (s != PSS_OK) return s;
+  if (n > PSS_MAX_KEYS) return fail(ctx, PSS_ERR_UNSUPPORTED, "n >= 2^31 is not supported");
+  PsrsPlan pp;
+  std::string err;
+  const pss_status ps = make_psrs_plan(key, val, n, n_blocks, n_parts, &pp, &err);
+  if (ps != PSS_OK) return fail(ctx, ps, err);
+  *bytes = pp.total;
+  return PSS_OK;
+}
+
+
+pss_status pss_psrs_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys_in,
+                         void *keys_out, const uint32_t *vals_in, uint32_t *vals_out, uint64_t n,
+                         uint32_t n_blocks, uint32_t n_parts, uint64_t *part_sizes, void *ws,
+                         size_t ws_bytes, void *stream) {
+  PsrsPlan pp;
+  pss_status st = psrs_prepare(ctx, key, val, keys_in, keys_out, vals_in, vals_out, n, n_blocks,
+                               n_parts, ws, ws_bytes, &pp);
+  if (st != PSS_OK) return st;
+  PSS_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  if (n == 0) {
+    if (part_sizes) PSS_TRY(hipMemsetAsync(part_sizes, 0, (size_t)n_parts * 8, s), "memset");
+    return PSS_OK;
+  }
+  PsrsOut o;
+  o.sizes = part_sizes;
+  return run_psrs(ctx, pp, (int)key, keys_in, vals_in, keys_out, vals_out, o, true, (char *)ws, s);
+}
+
+pss_status pss_psrs_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, uint64_t n,
+                              uint32_t n_blocks, uint32_t n_parts, void *sorted_blocks,
+                              void *samples, void *pivots, uint64_t *split, uint64_t *offsets,
+                              void *ws, size_t ws_bytes, void *stream) {
+  PsrsPlan pp;
+  const char dummy = 0;  // no key output: validate keys_in against a disjoint dummy
+  pss_status st = psrs_prepare(ctx, key, PSS_VAL_NONE, keys_in, n ? &dummy : nullptr, nullptr,
+                               nullptr, n, n_blocks, n_parts, ws, ws_bytes, &pp);
+  if (st != PSS_OK) return st;
+  PSS_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int kt = (int)key;
+  if (n == 0) {
+    if (pivots && n_parts > 1)
+      PSS_TRY(hipMemsetAsync(pivots, 0, (size_t)(n_parts - 1) * pss::key_bytes(kt), s), "memset");
+    if (split) PSS_TRY(hipMemsetAsync(split, 0, (size_t)n_blocks * (n_parts + 1) * 8, s), "memset");
+    if (offsets) PSS_TRY(hipMemsetAsync(offsets, 0, ((size_t)n_parts + 1) * 8, s), "memset");
+    return PSS_OK;
+  }
+  PsrsOut o;
+  o.sorted_blocks = sorted_blocks;
+  o.samples = samples;
+  o.pivots = n_parts > 1 ? pivots : nullptr;
+  o.split = split;
+  o.offsets = offsets;
+  return run_psrs(ctx, pp, kt, keys_in, nullptr, nullptr, nullptr, o, false, (char *)ws, s);
 }
 
 }  // extern "C"

@@ -82,12 +82,23 @@ struct RunGeom {
   SegTables seg;          // segmented mode (seg.off != nullptr)
   uint64_t row_bound;     // segmented mode: grid upper bound for rows
   uint64_t part_bound;    // segmented mode: grid upper bound for partitions
+  // Paper mode with partitions that follow the data (regular-sampling
+  // pivots): device arrays of the partitions' first ranks [n_parts + 1] and
+  // of the exclusive prefix over partitions of their chunk counts
+  // ceil(size / part_len) [n_parts + 1].  Table rows are then the chunk
+  // boundaries in order (at most chunk_bound chunks), not sub_per_part rows
+  // per partition.
+  const uint64_t *bounds;
+  const uint64_t *chunk_prefix;
+  uint64_t chunk_bound;
   uint64_t total_rows() const {
     if (seg.off) return row_bound;
+    if (paper && bounds) return chunk_bound + 1;
     return paper ? (uint64_t)n_parts * sub_per_part + 1 : n_groups * rows_per_group;
   }
   uint64_t total_parts() const {
     if (seg.off) return part_bound;
+    if (paper && bounds) return chunk_bound;
     return paper ? (uint64_t)n_parts * sub_per_part : n_groups * (rows_per_group - 1);
   }
 };
@@ -172,5 +183,21 @@ hipError_t launch_partition_offsets(const RunGeom &g, const uint32_t *table, uin
 hipError_t launch_split_table(const RunGeom &g, const uint32_t *table, uint64_t *split,
                               hipStream_t s);
 hipError_t launch_unmap_copy(int kt, const void *src, void *dst, uint64_t n, hipStream_t s);
+
+// Regular-sampling (PSRS) pivots over the sorted blocks of g (paper mode;
+// blocks hold mapped keys).  samples: n_P - 1 keys from each non-empty block.
+hipError_t launch_psrs_samples(int kt, const void *blocks, const RunGeom &g, void *samples,
+                               hipStream_t s);
+// From the sorted samples (ns keys): the pivots P_k = S[floor(k ns / n_P)],
+// the partition boundaries of every block (elements <= P_k), and the
+// partitions' first ranks bounds[0..n_P].  pivots (unmapped) and split
+// ([n_B][n_P + 1]) are optional outputs.
+hipError_t launch_psrs_partition(int kt, const void *blocks, const RunGeom &g,
+                                 const void *sorted_samples, uint64_t ns, uint64_t *bounds,
+                                 void *pivots, uint64_t *split, hipStream_t s);
+// Partition sizes (optional output) and the exclusive prefix of their chunk
+// counts, from bounds.
+hipError_t launch_psrs_chunks(const RunGeom &g, const uint64_t *bounds, uint64_t *sizes,
+                              uint64_t *chunks, uint64_t *chunk_prefix, hipStream_t s);
 
 }  // namespace pss

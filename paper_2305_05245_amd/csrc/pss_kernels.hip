@@ -685,6 +685,19 @@ struct RowInfo {
   bool valid;
 };
 
+// Paper partition holding chunk c (c < chunk_prefix[n_parts]): the largest p
+// with chunk_prefix[p] <= c (an empty partition shares its prefix with the
+// next one).
+__device__ __forceinline__ uint32_t chunk_partition(const RunGeom &g, uint64_t c) {
+  uint32_t lo = 0, hi = g.n_parts;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (g.chunk_prefix[mid] <= c) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 __device__ __forceinline__ RowInfo row_info(const RunGeom &g, uint64_t row, uint32_t *table) {
   RowInfo ri;
   ri.valid = true;
@@ -706,6 +719,21 @@ __device__ __forceinline__ RowInfo row_info(const RunGeom &g, uint64_t row, uint
     ri.grp = group_of(g, gi);
     const uint64_t r = k * g.part_len;
     ri.rank = r < ri.grp.len ? r : ri.grp.len;
+  } else if (g.bounds) {
+    ri.grp.gi = 0;
+    ri.grp.start = 0;
+    ri.grp.len = g.n;
+    // rows are the chunk boundaries: chunk c starts at rank bounds[p] +
+    // (c - chunk_prefix[p]) part_len; the last row is rank n
+    const uint64_t C = g.chunk_prefix[g.n_parts];
+    if (row > C) {
+      ri.valid = false;
+    } else if (row == C) {
+      ri.rank = g.n;
+    } else {
+      const uint32_t p = chunk_partition(g, row);
+      ri.rank = g.bounds[p] + (row - g.chunk_prefix[p]) * g.part_len;
+    }
   } else {
     ri.grp.gi = 0;
     ri.grp.start = 0;
@@ -823,6 +851,7 @@ __global__ __launch_bounds__(kCorankThreads) void corank_kernel(
   const uint32_t lane = threadIdx.x;
   const uint64_t row = blockIdx.x;
   const RowInfo ri = row_info(g, row, table);
+  if (!ri.valid) return;  // whole workgroup: rows beyond a data-dependent row count
   const uint64_t glen = ri.grp.len, R = g.run_len, r = ri.rank;
   const uint32_t nruns = glen ? (uint32_t)((glen + R - 1) / R) : 0;
   const uint32_t F = g.fan;
@@ -1284,6 +1313,18 @@ __device__ __forceinline__ PartInfo part_info(const RunGeom &g, uint64_t pidx,
     pi.group_len = grp.len;
     pi.out_off = grp.start + rlo;
     pi.lo_row = table + (gi * g.rows_per_group + k) * g.fan;
+    pi.hi_row = pi.lo_row + g.fan;
+  } else if (g.bounds) {
+    if (pidx >= g.chunk_prefix[g.n_parts]) return pi;
+    const uint32_t p = chunk_partition(g, pidx);
+    const uint64_t rp1 = g.bounds[p + 1];
+    const uint64_t lo = g.bounds[p] + (pidx - g.chunk_prefix[p]) * g.part_len;
+    const uint64_t hi = lo + g.part_len < rp1 ? lo + g.part_len : rp1;
+    pi.size = (uint32_t)(hi - lo);
+    pi.group_start = 0;
+    pi.group_len = g.n;
+    pi.out_off = lo;  // partitions follow each other: the output offset is the rank
+    pi.lo_row = table + pidx * g.fan;
     pi.hi_row = pi.lo_row + g.fan;
   } else {
     const uint64_t p = pidx / g.sub_per_part, i = pidx % g.sub_per_part;
@@ -1791,6 +1832,82 @@ __global__ void unmap_copy_kernel(const typename Key<KT>::U *__restrict__ src,
   if (i < n) dst[i] = Key<KT>::unmap(src[i]);
 }
 
+// ------------------------------------------- regular-sampling pivots ---
+// PSRS (Section 2.3): n_P - 1 samples at regular intervals of every sorted
+// block, the samples sorted, n_P - 1 pivots at regular intervals of them, and
+// every block cut by value (partition k: P_k < x <= P_{k+1}).  "Regular
+// intervals" of a sorted sequence of length len are its positions
+// floor(j len / n_P), j = 1..n_P-1; an empty block gives no samples.  Blocks
+// hold mapped keys, so all comparisons are unsigned.
+
+// One thread per sample: sample j of block b (only the first ceil(n / L)
+// blocks are non-empty, and they come first).
+template <typename U>
+__global__ void psrs_sample_kernel(const U *__restrict__ blocks, RunGeom g, U *__restrict__ samples,
+                                   uint64_t ns) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const uint64_t per = g.n_parts - 1;
+  const uint64_t b = i / per, j = i % per + 1;
+  const uint64_t L = g.run_len, start = b * L;
+  const uint64_t len = g.n - start < L ? g.n - start : L;
+  samples[i] = blocks[start + (j * len) / g.n_parts];
+}
+
+// One wave per boundary k = 0..n_P: lanes walk the blocks, each finds the
+// number of elements <= P_k of its block by binary search; the wave sums them
+// into bounds[k].  Boundaries 0 and n_P are the block ends.
+template <int KT>
+__global__ __launch_bounds__(256) void psrs_partition_kernel(
+    const typename Key<KT>::U *__restrict__ blocks, RunGeom g,
+    const typename Key<KT>::U *__restrict__ sorted_samples, uint64_t ns,
+    uint64_t *__restrict__ bounds, typename Key<KT>::U *__restrict__ pivots,
+    uint64_t *__restrict__ split) {
+  using U = typename Key<KT>::U;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t k = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t P = g.n_parts;
+  if (k > P) return;
+  const uint64_t L = g.run_len;
+  const bool inner = k > 0 && k < P && ns > 0;
+  const U piv = inner ? sorted_samples[(k * ns) / P] : U(0);
+  if (pivots && k > 0 && k < P && lane == 0) pivots[k - 1] = inner ? Key<KT>::unmap(piv) : U(0);
+  uint64_t sum = 0;
+  for (uint32_t b = lane; b < g.fan; b += 64) {
+    const uint64_t start = (uint64_t)b * L;
+    const uint64_t len = start >= g.n ? 0 : (g.n - start < L ? g.n - start : L);
+    uint64_t c;
+    if (k == 0 || (k < P && !inner)) {
+      c = 0;
+    } else if (k == P) {
+      c = len;
+    } else {
+      uint64_t lo = 0, hi = len;
+      while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (blocks[start + mid] <= piv) lo = mid + 1;
+        else hi = mid;
+      }
+      c = lo;
+    }
+    if (split) split[(uint64_t)b * (P + 1) + k] = c;
+    sum += c;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) sum += __shfl_xor(sum, d, 64);
+  if (lane == 0) bounds[k] = sum;
+}
+
+// Partition sizes and their chunk counts ceil(size / part_len).
+__global__ void psrs_chunks_kernel(RunGeom g, const uint64_t *__restrict__ bounds,
+                                   uint64_t *__restrict__ sizes, uint64_t *__restrict__ chunks) {
+  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.n_parts) return;
+  const uint64_t m = bounds[p + 1] - bounds[p];
+  if (sizes) sizes[p] = m;
+  chunks[p] = (m + g.part_len - 1) / g.part_len;
+}
+
 // ------------------------------------------------- segmented planning ---
 // One workgroup reads the segment offsets, checks them, and writes per
 // segment: its tile class and tiles, merge passes, samples, and per pass the
@@ -2166,6 +2283,46 @@ hipError_t launch_split_table(const RunGeom &g, const uint32_t *table, uint64_t 
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(split_table_kernel, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, g,
                      table, split);
+  return hipGetLastError();
+}
+
+hipError_t launch_psrs_samples(int kt, const void *blocks, const RunGeom &g, void *samples,
+                               hipStream_t s) {
+  if (g.n == 0 || g.n_parts < 2) return hipSuccess;
+  const uint64_t nonempty = (g.n + g.run_len - 1) / g.run_len;
+  const uint64_t ns = nonempty * (g.n_parts - 1);
+  const uint32_t grid = (uint32_t)((ns + 255) / 256);
+  if (key_bytes(kt) == 8)
+    hipLaunchKernelGGL((psrs_sample_kernel<uint64_t>), dim3(grid), dim3(256), 0, s,
+                       (const uint64_t *)blocks, g, (uint64_t *)samples, ns);
+  else
+    hipLaunchKernelGGL((psrs_sample_kernel<uint32_t>), dim3(grid), dim3(256), 0, s,
+                       (const uint32_t *)blocks, g, (uint32_t *)samples, ns);
+  return hipGetLastError();
+}
+
+hipError_t launch_psrs_partition(int kt, const void *blocks, const RunGeom &g,
+                                 const void *sorted_samples, uint64_t ns, uint64_t *bounds,
+                                 void *pivots, uint64_t *split, hipStream_t s) {
+  const uint32_t grid = (uint32_t)(((uint64_t)g.n_parts + 1 + 3) / 4);
+  return dispatch_kt(kt, [&](auto ktc) {
+    constexpr int KT = decltype(ktc)::value;
+    using U = typename Key<KT>::U;
+    hipLaunchKernelGGL((psrs_partition_kernel<KT>), dim3(grid), dim3(256), 0, s,
+                       (const U *)blocks, g, (const U *)sorted_samples, ns, bounds, (U *)pivots,
+                       split);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_psrs_chunks(const RunGeom &g, const uint64_t *bounds, uint64_t *sizes,
+                              uint64_t *chunks, uint64_t *chunk_prefix, hipStream_t s) {
+  hipLaunchKernelGGL(psrs_chunks_kernel, dim3((uint32_t)((g.n_parts + 255) / 256)), dim3(256), 0,
+                     s, g, bounds, sizes, chunks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(exclusive_scan_u64_kernel, dim3(1), dim3(1024), 0, s, (const uint64_t *)chunks,
+                     chunk_prefix, (uint64_t)g.n_parts);
   return hipGetLastError();
 }
 

@@ -140,6 +140,89 @@ def bench_key_value(pss, torch, log2n: int, steps: int, warmup: int) -> dict:
             "ms": round(dt * 1e3, 3), "gkeys_per_s": round(n / dt / 1e9, 3)}
 
 
+STEP1 = ("tile_sort", "sample_split_search", "sample_merge", "split_search", "merge")
+PIVOTS = {"pses": ("partition_search", "offset_scan"),
+          "psrs": ("psrs_samples", "psrs_sample_sort", "psrs_partition", "psrs_chunks",
+                   "partition_search")}
+
+
+def _time_split_method(pss, torch, run, steps: int, warmup: int, method: str) -> tuple:
+    """Wall time per call of run() and one profiled call's library times."""
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    pss.profile(True)
+    pss.profile_read()
+    sizes = run()
+    prof = pss.profile_read()
+    pss.profile(False)
+
+    def ms(names):
+        return round(sum(prof[x]["ms"] for x in names if x in prof), 4)
+
+    return dt, sizes, {"step1_block_sort_ms": ms(STEP1),
+                       "step23_pivots_partition_ms": ms(PIVOTS[method]),
+                       "step4_merge_ms": ms(("partition_merge",))}
+
+
+def bench_splitting(pss, torch, log2n: int, steps: int, warmup: int,
+                    nbps: tuple = (64, 256)) -> dict:
+    """The paper's single level with n_B = n_P = b for each b in nbps, exact
+    splitting (PSES) against regular-sampling pivots (PSRS), on uniform int64
+    keys (seed 2) and Duplicate3 keys {0, 1, 2} as int64 (seed 16): time per
+    sort, library time per step (1: block sort; 2-3: pivots and partition
+    boundaries, including the co-rank rows that cut partitions into merge
+    chunks; 4: the merge), and partition sizes.  With one worker per partition,
+    as in the paper, the merge's parallel efficiency is at most mean/max of the
+    sizes.  The two outputs must agree bit for bit."""
+    import numpy as np
+
+    import workloads as W
+    from paper_2305_05245_amd import _lib
+
+    n = 1 << log2n
+    ws = torch.empty(max(max(_lib.workspace_bytes(_lib.I64, _lib.VAL_NONE, n, b, b),
+                             _lib.psrs_workspace_bytes(_lib.I64, _lib.VAL_NONE, n, b, b))
+                         for b in nbps), dtype=torch.uint8, device="cuda")
+    out_e = torch.empty(n, dtype=torch.int64, device="cuda")
+    out_r = torch.empty_like(out_e)
+    res = {"workload": f"paper single level, 2^{log2n} int64 keys, n_B = n_P in {list(nbps)}"}
+    gens = {"uniform": lambda: W.uniform_i64(n, seed=2),
+            "duplicate3": lambda: W.duplicate3_u32(n, seed=16).astype(np.int64)}
+    for dist, gen in gens.items():
+        keys = torch.from_numpy(gen()).cuda()
+        for nbp in nbps:
+            def run_pses():
+                pss.sort(keys, n_blocks=nbp, n_parts=nbp, out=out_e, workspace=ws)
+                # exact splitting: O_k = r_k = floor(kN/n_P) (checked on the device)
+                return np.diff(np.array([k * n // nbp for k in range(nbp + 1)], dtype=np.int64))
+
+            def run_psrs():
+                _, _, sizes = pss.psrs_sort(keys, n_blocks=nbp, n_parts=nbp, out=out_r,
+                                            workspace=ws)
+                return sizes
+
+            row = {}
+            for method, run in (("pses", run_pses), ("psrs", run_psrs)):
+                dt, sizes, steps_ms = _time_split_method(pss, torch, run, steps, warmup, method)
+                sz = sizes if isinstance(sizes, np.ndarray) else sizes.cpu().numpy()
+                row[method] = {
+                    "ms": round(dt * 1e3, 3), "gkeys_per_s": round(n / dt / 1e9, 3), **steps_ms,
+                    "max_partition": int(sz.max()), "nonempty_partitions": int(np.count_nonzero(sz)),
+                    "one_worker_merge_efficiency_bound": round(float(sz.mean() / sz.max()), 4),
+                }
+            assert torch.equal(out_e, out_r), f"PSES and PSRS outputs differ ({dist}, {nbp})"
+            assert pss.device_check(0) == 0
+            res[f"{dist}_nb{nbp}"] = row
+        del keys
+    return res
+
+
 def bench_batched(pss, torch, steps: int, warmup: int) -> dict:
     """4096 int64 arrays of round(2^U) keys, U ~ Uniform[6, 20] (seed 12), keys
     uniform over the full range (seed 13): the segmented sort replayed from one
@@ -337,7 +420,9 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-array batch")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=20000)
-    ap.add_argument("--leg", choices=("batched", "serving", "key_value"),
+    ap.add_argument("--no-splitting", action="store_true",
+                    help="skip the exact-splitting vs regular-sampling comparison")
+    ap.add_argument("--leg", choices=("batched", "serving", "key_value", "splitting"),
                     help="run only this leg and print its JSON object (for profiling)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a plain device-to-device copy of the keys (bandwidth and "
@@ -362,6 +447,10 @@ def main() -> int:
 
     if args.leg == "key_value":
         print(json.dumps(bench_key_value(pss, torch, args.log2n, max(3, args.steps // 2), 1)),
+              flush=True)
+        return 0
+    if args.leg == "splitting":
+        print(json.dumps(bench_splitting(pss, torch, args.log2n, max(3, args.steps // 2), 1)),
               flush=True)
         return 0
     if args.leg == "batched":
@@ -468,6 +557,10 @@ def main() -> int:
         torch.cuda.empty_cache()
         print("[bench] batched segmented sort", file=sys.stderr, flush=True)
         line["batched"] = bench_batched(pss, torch, max(3, args.steps // 2), 1)
+        torch.cuda.empty_cache()
+    if not args.no_splitting:
+        print("[bench] exact splitting vs regular sampling", file=sys.stderr, flush=True)
+        line["splitting"] = bench_splitting(pss, torch, args.log2n, max(3, args.steps // 2), 1)
         torch.cuda.empty_cache()
     if not args.no_serving:
         print("[bench] serving loop", file=sys.stderr, flush=True)

@@ -221,7 +221,8 @@ def splitters(keys: torch.Tensor, n_blocks: int, n_parts: int,
 
 def psrs_sort(keys: torch.Tensor, vals: torch.Tensor | None = None, n_blocks: int = 64,
               n_parts: int = 64, key_type: str | int | None = None,
-              out: torch.Tensor | None = None, vals_out: torch.Tensor | None = None):
+              out: torch.Tensor | None = None, vals_out: torch.Tensor | None = None,
+              workspace: torch.Tensor | None = None):
     """The paper's single level with regular-sampling (PSRS) pivots instead of
     exact splitting: same output as `sort`, partition sizes that follow the
     data.  Returns (sorted_keys, sorted_vals or None, partition_sizes [n_P]
@@ -243,7 +244,8 @@ def psrs_sort(keys: torch.Tensor, vals: torch.Tensor | None = None, n_blocks: in
     if vals is not None and vals_out is None:
         vals_out = torch.empty_like(vals)
     sizes = torch.empty(n_parts, dtype=torch.int64, device=keys.device)
-    ws = Workspace.get(dev, _lib.psrs_workspace_bytes(kt, vt, n, n_blocks, n_parts))
+    need = _lib.psrs_workspace_bytes(kt, vt, n, n_blocks, n_parts)
+    ws = workspace if workspace is not None else Workspace.get(dev, need)
     _context(dev).psrs_sort(kt, vt, keys.data_ptr(), out.data_ptr(),
                             vals.data_ptr() if vals is not None else 0,
                             vals_out.data_ptr() if vals is not None else 0, n, n_blocks, n_parts,

@@ -457,11 +457,11 @@ pss_status run_psrs(pss_ctx *ctx, const PsrsPlan &pp, int kt, const void *keys_i
   top.chunk_prefix = cprefix;
   uint32_t *table = (uint32_t *)(w + pp.off_table);
   {
-    LaunchTimer t(ctx, "split_search", top.total_rows() * top.fan * 4, s);
+    LaunchTimer t(ctx, "partition_search", top.total_rows() * top.fan * 4, s);
     PSS_TRY(pss::launch_corank(kt, blocks, top, table, nullptr, nullptr, s), "chunk split launch");
   }
   {
-    LaunchTimer t(ctx, "merge", 2 * p.n * ((uint64_t)p.kb + (p.kv ? 4 : 0)), s);
+    LaunchTimer t(ctx, "partition_merge", 2 * p.n * ((uint64_t)p.kb + (p.kv ? 4 : 0)), s);
     PSS_TRY(pss::launch_merge(kt, p.kv ? 1 : 0, blocks, vbuf[P], keys_out, vals_out, top, table,
                               nullptr, 1, nullptr, nullptr, s),
             "merge launch");
@@ -682,7 +682,7 @@ pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys
     uint64_t *offsets = (uint64_t *)(w + p.off_offsets);
     const uint64_t sweep = 2 * p.n * ((uint64_t)p.kb + (p.kv ? 4 : 0));
     {
-      LaunchTimer t(ctx, "split_search", p.top.total_rows() * p.top.fan * 4, s);
+      LaunchTimer t(ctx, "partition_search", p.top.total_rows() * p.top.fan * 4, s);
       PSS_TRY(pss::launch_corank(kt, kb[P], p.top, table, nullptr, nullptr, s), "splitter launch");
     }
     {
@@ -690,7 +690,7 @@ pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys
       PSS_TRY(pss::launch_partition_offsets(p.top, table, sizes, offsets, s), "offset scan launch");
     }
     {
-      LaunchTimer t(ctx, "merge", sweep, s);
+      LaunchTimer t(ctx, "partition_merge", sweep, s);
       PSS_TRY(pss::launch_merge(kt, p.kv ? 1 : 0, kb[P], vb[P], keys_out, vals_out, p.top, table,
                                 offsets, 1, nullptr, nullptr, s),
               "merge launch");

@@ -822,6 +822,77 @@ __device__ void block_exclusive_scan(uint32_t *a, uint32_t n, uint32_t *wsum) {
   __syncthreads();
 }
 
+// Compare-exchange of two (key, tie) slots, ascending when `up`.
+template <typename U, int E>
+__device__ __forceinline__ void cas(U &ka, uint32_t &ta, U &kb, uint32_t &tb, bool up) {
+  const bool gt = ka > kb || (ka == kb && ta > tb);
+  if (gt == up) {
+    const U k = ka;
+    ka = kb;
+    kb = k;
+    const uint32_t t = ta;
+    ta = tb;
+    tb = t;
+  }
+}
+
+// One compare-exchange stage of the wave's bitonic sort at lane distance D
+// (slot s = lane + 64 e; sort block k; ascending by (key, tie)).
+template <int D, typename U, int E>
+__device__ __forceinline__ void bitonic_lane_stage(U (&key)[E], uint32_t (&tie)[E], uint32_t lane,
+                                                   uint32_t k, uint32_t Cp) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (64u * e < Cp) {
+      const U ok = shfl_xor_c<D>(key[e]);
+      const uint32_t ot = shfl_xor_c<D>(tie[e]);
+      const uint32_t idx = lane + 64u * e;
+      const bool lower = (lane & D) == 0;
+      const bool up = (idx & k) == 0;
+      const bool mine_gt = key[e] > ok || (key[e] == ok && tie[e] > ot);
+      // the lower slot keeps the smaller when ascending
+      const bool take_other = (lower == up) ? mine_gt : !mine_gt;
+      key[e] = take_other ? ok : key[e];
+      tie[e] = take_other ? ot : tie[e];
+    }
+  }
+}
+
+// Slot stage of the same bitonic sort at lane distance 64 DE: slots e and
+// e + DE of one lane (every e with bit DE clear).
+template <int DE, typename U, int E>
+__device__ __forceinline__ void bitonic_slot_stage(U (&key)[E], uint32_t (&tie)[E], uint32_t lane,
+                                                   uint32_t k, uint32_t Cp) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if ((e & DE) == 0 && (e | DE) < E && 64u * (e | DE) < Cp) {
+      const bool up = ((lane + 64u * e) & k) == 0;
+      cas<U, E>(key[e], tie[e], key[(e | DE) & (E - 1)], tie[(e | DE) & (E - 1)], up);
+    }
+  }
+}
+
+// Ascending bitonic sort by (key, tie) of the Cp (a power of two, >= 64)
+// slots s = lane + 64 e of one wave: distances of 64 and more exchange slots
+// inside a lane, smaller ones exchange lanes.
+template <typename U, int E>
+__device__ __forceinline__ void bitonic_sort_slots(U (&key)[E], uint32_t (&tie)[E], uint32_t lane,
+                                                   uint32_t Cp) {
+  for (uint32_t k = 2; k <= Cp; k <<= 1) {
+    if constexpr (E > 16) if (k >= 128u * 16) bitonic_slot_stage<16>(key, tie, lane, k, Cp);
+    if constexpr (E > 8) if (k >= 128u * 8) bitonic_slot_stage<8>(key, tie, lane, k, Cp);
+    if constexpr (E > 4) if (k >= 128u * 4) bitonic_slot_stage<4>(key, tie, lane, k, Cp);
+    if constexpr (E > 2) if (k >= 128u * 2) bitonic_slot_stage<2>(key, tie, lane, k, Cp);
+    if constexpr (E > 1) if (k >= 128u) bitonic_slot_stage<1>(key, tie, lane, k, Cp);
+    if (k > 32) bitonic_lane_stage<32>(key, tie, lane, k, Cp);
+    if (k > 16) bitonic_lane_stage<16>(key, tie, lane, k, Cp);
+    if (k > 8) bitonic_lane_stage<8>(key, tie, lane, k, Cp);
+    if (k > 4) bitonic_lane_stage<4>(key, tie, lane, k, Cp);
+    if (k > 2) bitonic_lane_stage<2>(key, tie, lane, k, Cp);
+    bitonic_lane_stage<1>(key, tie, lane, k, Cp);
+  }
+}
+
 // --------------------------------------------------------------- K2/K3 ---
 // Exact co-rank of one target rank r over the F sorted runs of one group:
 // t_b = number of keys of run b among the r smallest keys of the group, where
@@ -839,12 +910,16 @@ __device__ void block_exclusive_scan(uint32_t *a, uint32_t n, uint32_t *wsum) {
 // and V_j(Q)_b is within [2 V_{j+1}(Q_lo(j+1))_b, 2 V_{j+1}(Q_hi(j+1))_b + 1].
 // So each level loads fewer than 3F candidate samples, sorts them in LDS and
 // reads both prefixes off; at level 0, Q_lo = Q_hi = r and V_0(r) = t.
-template <typename U, uint32_t MAXF>
+//
+// E > 0: the candidates are sorted in registers, E slots per lane (slot s =
+// lane + 64 e, at most 64 E candidates), sTie holding each slot's run while
+// they are loaded; E = 0: they are sorted in LDS (CMAX of them).
+template <typename U, uint32_t MAXF, int E>
 __global__ __launch_bounds__(kCorankThreads) void corank_kernel(
     const U *__restrict__ src, RunGeom g, uint32_t *__restrict__ table,
     U *__restrict__ pivots, uint64_t *__restrict__ counts, int kt) {
-  constexpr uint32_t CMAX = MAXF <= 64 ? 256 : (MAXF <= 512 ? 2048 : 8192);
-  __shared__ U sKey[CMAX];
+  constexpr uint32_t CMAX = E > 0 ? 64 * E : (MAXF <= 64 ? 256 : (MAXF <= 512 ? 2048 : 8192));
+  __shared__ U sKey[E > 0 ? 1 : CMAX];
   __shared__ uint32_t sTie[CMAX];
   __shared__ uint32_t sA[MAXF], sB[MAXF], sCnt[2 * MAXF], sOff[MAXF + 1];
 
@@ -899,62 +974,126 @@ __global__ __launch_bounds__(kCorankThreads) void corank_kernel(
       if (lane == 0) report(kErrCandidates);
       C = CMAX;
     }
-    uint32_t Cp = 1;
-    while (Cp < C) Cp <<= 1;
-
-    for (uint32_t b = lane; b < nruns; b += 64) {
-      const uint32_t c = sOff[b + 1] - sOff[b];
-      const uint64_t run_start = ri.grp.start + (uint64_t)b * R;
-      const uint32_t first = 2 * sA[b] + 1;
-      for (uint32_t x = 0; x < c; ++x) {
-        const uint32_t s = sOff[b] + x;
-        if (s < CMAX) {
-          sKey[s] = src[run_start + (uint64_t)(first + x) * h - 1];
-          sTie[s] = (b << 20) | x;
+    if constexpr (E > 0) {
+      uint32_t Cp = 64;
+      while (Cp < C) Cp <<= 1;
+      for (uint32_t b = lane; b < nruns; b += 64) {
+        const uint32_t o = sOff[b], c = sOff[b + 1] - o;
+        for (uint32_t x = 0; x < c; ++x)
+          if (o + x < CMAX) sTie[o + x] = b;
+      }
+      for (uint32_t b = lane; b < 2 * nruns; b += 64) sCnt[b] = 0;
+      __syncthreads();
+      U key[E];
+      uint32_t tie[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const uint32_t s = lane + 64u * e;
+        key[e] = key_max<U>();
+        tie[e] = 0xffffffffu;
+        if (s < C) {
+          const uint32_t b = sTie[s];
+          const uint32_t x = s - sOff[b];
+          key[e] = src[ri.grp.start + (uint64_t)b * R + (uint64_t)(2 * sA[b] + 1 + x) * h - 1];
+          tie[e] = (b << 20) | x;
         }
       }
-    }
-    for (uint32_t s = C + lane; s < Cp && s < CMAX; s += 64) {
-      sKey[s] = key_max<U>();
-      sTie[s] = 0xffffffffu;
-    }
-    for (uint32_t b = lane; b < 2 * nruns; b += 64) sCnt[b] = 0;
-    __syncthreads();
+      bitonic_sort_slots<U, E>(key, tie, lane, Cp);
+      uint64_t rho_lo = q_lo - base, rho_hi = q_hi - base;
+      if (q_lo < base || q_hi < base || rho_hi > C || rho_lo > rho_hi) {  // bracket broken
+        if (lane == 0) report(kErrBracket);
+        rho_lo = rho_lo > C ? C : rho_lo;
+        rho_hi = rho_hi > C ? C : rho_hi;
+        rho_lo = rho_lo > rho_hi ? rho_hi : rho_lo;
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const uint32_t s = lane + 64u * e;
+        if (s < rho_hi) {
+          const uint32_t b = tie[e] >> 20;
+          atomicAdd(&sCnt[2 * b + 1], 1u);
+          if (s < rho_lo) atomicAdd(&sCnt[2 * b], 1u);
+        }
+      }
+      __syncthreads();
+    } else {
+      uint32_t Cp = 1;
+      while (Cp < C) Cp <<= 1;
 
-    // bitonic sort of (key, tie) pairs, ascending
-    for (uint32_t k = 2; k <= Cp; k <<= 1) {
-      for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
-        for (uint32_t t = lane; t < Cp / 2; t += 64) {
-          const uint32_t i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
-          const uint32_t l = i + jj;
-          const U ki = sKey[i], kl = sKey[l];
-          const uint32_t ti = sTie[i], tl = sTie[l];
-          const bool gt = ki > kl || (ki == kl && ti > tl);
-          const bool up = (i & k) == 0;
-          if (gt == up) {
-            sKey[i] = kl;
-            sKey[l] = ki;
-            sTie[i] = tl;
-            sTie[l] = ti;
+      // slot -> run in sTie first, then every lane loads slots lane, lane + 64,
+      // ... with a batch of loads in flight (each slot is read and rewritten by
+      // the one lane that owns it)
+      for (uint32_t b = lane; b < nruns; b += 64) {
+        const uint32_t o = sOff[b], c = sOff[b + 1] - o;
+        for (uint32_t x = 0; x < c; ++x)
+          if (o + x < CMAX) sTie[o + x] = b;
+      }
+      __syncthreads();
+      constexpr uint32_t kBatch = 8;
+      for (uint32_t s0 = 0; s0 < C; s0 += 64 * kBatch) {
+        U v[kBatch];
+        uint32_t t[kBatch];
+  #pragma unroll
+        for (uint32_t u = 0; u < kBatch; ++u) {
+          const uint32_t s = s0 + u * 64 + lane;
+          if (s < C) {
+            const uint32_t b = sTie[s];
+            const uint32_t x = s - sOff[b];
+            v[u] = src[ri.grp.start + (uint64_t)b * R + (uint64_t)(2 * sA[b] + 1 + x) * h - 1];
+            t[u] = (b << 20) | x;
           }
         }
-        __syncthreads();
+  #pragma unroll
+        for (uint32_t u = 0; u < kBatch; ++u) {
+          const uint32_t s = s0 + u * 64 + lane;
+          if (s < C) {
+            sKey[s] = v[u];
+            sTie[s] = t[u];
+          }
+        }
       }
-    }
+      for (uint32_t s = C + lane; s < Cp && s < CMAX; s += 64) {
+        sKey[s] = key_max<U>();
+        sTie[s] = 0xffffffffu;
+      }
+      for (uint32_t b = lane; b < 2 * nruns; b += 64) sCnt[b] = 0;
+      __syncthreads();
 
-    uint64_t rho_lo = q_lo - base, rho_hi = q_hi - base;
-    if (q_lo < base || q_hi < base || rho_hi > C || rho_lo > rho_hi) {  // bracket broken
-      if (lane == 0) report(kErrBracket);
-      rho_lo = rho_lo > C ? C : rho_lo;
-      rho_hi = rho_hi > C ? C : rho_hi;
-      rho_lo = rho_lo > rho_hi ? rho_hi : rho_lo;
+      // bitonic sort of (key, tie) pairs, ascending
+      for (uint32_t k = 2; k <= Cp; k <<= 1) {
+        for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+          for (uint32_t t = lane; t < Cp / 2; t += 64) {
+            const uint32_t i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
+            const uint32_t l = i + jj;
+            const U ki = sKey[i], kl = sKey[l];
+            const uint32_t ti = sTie[i], tl = sTie[l];
+            const bool gt = ki > kl || (ki == kl && ti > tl);
+            const bool up = (i & k) == 0;
+            if (gt == up) {
+              sKey[i] = kl;
+              sKey[l] = ki;
+              sTie[i] = tl;
+              sTie[l] = ti;
+            }
+          }
+          __syncthreads();
+        }
+      }
+
+      uint64_t rho_lo = q_lo - base, rho_hi = q_hi - base;
+      if (q_lo < base || q_hi < base || rho_hi > C || rho_lo > rho_hi) {  // bracket broken
+        if (lane == 0) report(kErrBracket);
+        rho_lo = rho_lo > C ? C : rho_lo;
+        rho_hi = rho_hi > C ? C : rho_hi;
+        rho_lo = rho_lo > rho_hi ? rho_hi : rho_lo;
+      }
+      for (uint64_t s = lane; s < rho_hi; s += 64) {
+        const uint32_t b = sTie[s] >> 20;
+        atomicAdd(&sCnt[2 * b + 1], 1u);
+        if (s < rho_lo) atomicAdd(&sCnt[2 * b], 1u);
+      }
+      __syncthreads();
     }
-    for (uint64_t s = lane; s < rho_hi; s += 64) {
-      const uint32_t b = sTie[s] >> 20;
-      atomicAdd(&sCnt[2 * b + 1], 1u);
-      if (s < rho_lo) atomicAdd(&sCnt[2 * b], 1u);
-    }
-    __syncthreads();
     for (uint32_t b = lane; b < nruns; b += 64) {
       const uint32_t a = sA[b];
       sA[b] = 2 * a + sCnt[2 * b];
@@ -1010,46 +1149,6 @@ __global__ __launch_bounds__(kCorankThreads) void corank_kernel(
   }
 }
 
-// Same search for groups of at most 64 runs, one lane per run: the prefix
-// bounds live in registers, each level's candidates are loaded one per slot
-// by all lanes at once and sorted in registers by a bitonic network across the
-// wave (slot s = lane + 64 e), and the two prefix counts are read off with LDS
-// atomics.  E = largest number of slots per lane (3 * 64 candidates < 64 * 4).
-template <typename U, int E>
-__device__ __forceinline__ void cas(U &ka, uint32_t &ta, U &kb, uint32_t &tb, bool up) {
-  const bool gt = ka > kb || (ka == kb && ta > tb);
-  if (gt == up) {
-    const U k = ka;
-    ka = kb;
-    kb = k;
-    const uint32_t t = ta;
-    ta = tb;
-    tb = t;
-  }
-}
-
-// One compare-exchange stage of the wave's bitonic sort at lane distance D
-// (slot s = lane + 64 e; sort block k; ascending by (key, tie)).
-template <int D, typename U, int E>
-__device__ __forceinline__ void bitonic_lane_stage(U (&key)[E], uint32_t (&tie)[E], uint32_t lane,
-                                                   uint32_t k, uint32_t Cp) {
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    if (64u * e < Cp) {
-      const U ok = shfl_xor_c<D>(key[e]);
-      const uint32_t ot = shfl_xor_c<D>(tie[e]);
-      const uint32_t idx = lane + 64u * e;
-      const bool lower = (lane & D) == 0;
-      const bool up = (idx & k) == 0;
-      const bool mine_gt = key[e] > ok || (key[e] == ok && tie[e] > ot);
-      // the lower slot keeps the smaller when ascending
-      const bool take_other = (lower == up) ? mine_gt : !mine_gt;
-      key[e] = take_other ? ok : key[e];
-      tie[e] = take_other ? ot : tie[e];
-    }
-  }
-}
-
 // Merged samples of one pass: the group's level-kSampleLog2 samples in
 // (key, run, position) order as run ids, plus per-run prefix counts at every
 // kChunk-th merged sample.  They give V_5(Q) for any Q without a search.
@@ -1059,6 +1158,11 @@ struct SampleIndex {
   RunGeom gs;             // geometry of the sample array (groups align with data)
 };
 
+// Same search for groups of at most 64 runs, one lane per run: the prefix
+// bounds live in registers, each level's candidates are loaded one per slot
+// by all lanes at once and sorted in registers by a bitonic network across the
+// wave (slot s = lane + 64 e), and the two prefix counts are read off with LDS
+// atomics.  E = largest number of slots per lane (3 * 64 candidates < 64 * 4).
 template <typename U, int E, bool SAMPLED>
 __global__ __launch_bounds__(kCorankThreads) void corank_wave_kernel(
     const U *__restrict__ src_primary, const U *__restrict__ src_alt, RunGeom g,
@@ -2155,11 +2259,14 @@ hipError_t launch_corank(int kt, const void *src, const RunGeom &g, uint32_t *ta
   const uint64_t rows = g.total_rows();
   if (rows == 0) return hipSuccess;
   if (!src_alt) src_alt = src;
+  // up to 512 runs the (fewer than 3 * fan) candidates are sorted in
+  // registers, 64 * E slots; beyond, in LDS
   auto go = [&](auto u, auto maxf) -> hipError_t {
     using U = decltype(u);
     constexpr uint32_t MAXF = decltype(maxf)::value;
-    hipLaunchKernelGGL((corank_kernel<U, MAXF>), dim3((uint32_t)rows), dim3(kCorankThreads), 0, s,
-                       (const U *)src, g, table, (U *)pivots, counts, kt);
+    constexpr int E = MAXF <= 512 ? (int)(MAXF / 16) : 0;
+    hipLaunchKernelGGL((corank_kernel<U, MAXF, E>), dim3((uint32_t)rows), dim3(kCorankThreads), 0,
+                       s, (const U *)src, g, table, (U *)pivots, counts, kt);
     return hipGetLastError();
   };
   const bool wide = key_bytes(kt) == 8;
@@ -2179,6 +2286,12 @@ hipError_t launch_corank(int kt, const void *src, const RunGeom &g, uint32_t *ta
     return wide ? wave(uint64_t{}, E4{}) : wave(uint32_t{}, E4{});
   }
   if (g.seg.off) return hipErrorInvalidValue;
+  if (g.fan <= 128)
+    return wide ? go(uint64_t{}, std::integral_constant<uint32_t, 128>{})
+                : go(uint32_t{}, std::integral_constant<uint32_t, 128>{});
+  if (g.fan <= 256)
+    return wide ? go(uint64_t{}, std::integral_constant<uint32_t, 256>{})
+                : go(uint32_t{}, std::integral_constant<uint32_t, 256>{});
   if (g.fan <= 512)
     return wide ? go(uint64_t{}, std::integral_constant<uint32_t, 512>{})
                 : go(uint32_t{}, std::integral_constant<uint32_t, 512>{});

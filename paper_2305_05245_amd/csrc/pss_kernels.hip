@@ -1498,7 +1498,9 @@ __global__ __launch_bounds__(NT, (VMODE == 0 && NT > kMergeThreads) ? 2 : 1) voi
   // chunk prefixes over pairs, for each merge round (fan <= 64: 6 rounds)
   __shared__ uint32_t cpre[MAXF <= 64 ? 6 * 33 : 1];
   __shared__ uint64_t ssrc[MAXF];
-  __shared__ uint32_t sseg[MAXF <= 64 ? kPart / 4 : 1];  // segment of each position, bytes
+  // segment of each position, one byte each (up to 256 segments)
+  constexpr bool LABELS = MAXF <= 256;
+  __shared__ uint32_t sseg[LABELS ? kPart / 4 : 1];
   __shared__ uint32_t wsum[NT / 64 + 1];
   __shared__ uint32_t hist[VMODE == 2 ? (kPart / kChunk) * kMaxSampledFan : 1];
 
@@ -1574,7 +1576,7 @@ __global__ __launch_bounds__(NT, (VMODE == 0 && NT > kMergeThreads) ? 2 : 1) voi
     uint64_t addr[ITEMS];
     uint32_t runid[VMODE == 2 ? ITEMS : 1];
     uint32_t lpos[ITEMS];  // LDS slot of each item
-    if constexpr (MAXF <= 64) {
+    if constexpr (LABELS) {
       // Label every position with its segment (one byte each): thread t
       // labels positions 16t..16t+15, so each item below finds its segment
       // with one independent LDS read instead of a walk over the offsets.
@@ -2372,6 +2374,9 @@ hipError_t launch_merge(int kt, int vmode, const void *src, const uint32_t *vsrc
       return kv ? go(std::integral_constant<int, 1>{}, std::integral_constant<uint32_t, 64>{})
                 : go(std::integral_constant<int, 0>{}, std::integral_constant<uint32_t, 64>{});
     if (g.seg.off) return hipErrorInvalidValue;
+    if (g.fan <= 256)
+      return kv ? go(std::integral_constant<int, 1>{}, std::integral_constant<uint32_t, 256>{})
+                : go(std::integral_constant<int, 0>{}, std::integral_constant<uint32_t, 256>{});
     if (g.fan <= kMaxRuns)
       return kv ? go(std::integral_constant<int, 1>{}, std::integral_constant<uint32_t, kMaxRuns>{})
                 : go(std::integral_constant<int, 0>{}, std::integral_constant<uint32_t, kMaxRuns>{});

@@ -47,6 +47,7 @@ ERRORS = {
     14: "offset O_k != r_k",
     15: "partition size not floor/ceil(N/n_P)",
     16: "no pivot candidate",
+    17: "sorted indices are not a permutation",
 }
 
 
@@ -78,6 +79,8 @@ def bind(path: str):
     lib.oracle_psrs.argtypes = [ctypes.c_int, u64, vp, vp, u32, u32, vp, vp,
                                 vp, vp, vp, vp, vp, vp]
     lib.oracle_psrs.restype = ctypes.c_int
+    lib.oracle_sort_records.argtypes = [ctypes.c_int, u64, vp, u32, u32, u32, u32, vp]
+    lib.oracle_sort_records.restype = ctypes.c_int
     lib.oracle_rank_counts.argtypes = [ctypes.c_int, u64, vp, u64, vp, vp]
     lib.oracle_rank_counts.restype = None
     return lib
@@ -193,6 +196,22 @@ def psrs(keys: np.ndarray, n_blocks: int, n_parts: int, vals: np.ndarray | None 
     if rc != 0:
         raise RuntimeError(f"oracle_psrs failed: {ERRORS.get(rc, rc)}")
     return PsrsResult(out, vout, blocks, samples[:ns.value].copy(), pivots, split, offsets)
+
+
+def sort_records(records: np.ndarray, key_dtype: str, key_offset: int, n_blocks: int = 16,
+                 n_parts: int = 16, lib=None) -> np.ndarray:
+    """Records (a 2-D uint8 array, one row per record) sorted stably by the key
+    of type `key_dtype` at byte `key_offset` of each row."""
+    rec = np.ascontiguousarray(records, dtype=np.uint8)
+    n, rb = rec.shape
+    out = np.empty_like(rec)
+    rc = (lib or _load()).oracle_sort_records(dtype_code(key_dtype), n,
+                                              rec.ctypes.data_as(ctypes.c_void_p), rb, key_offset,
+                                              n_blocks, n_parts,
+                                              out.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise RuntimeError(f"oracle_sort_records failed: {ERRORS.get(rc, rc)}")
+    return out
 
 
 def rank_counts(keys: np.ndarray, v, lib=None) -> tuple[int, int]:

@@ -545,3 +545,51 @@ done:
   free(seg); free(seg_len); free(merged);
   return rc;
 }
+
+/* ------------------------------------- records sorted by a key field ---- */
+
+/* Fixed-size records (Table 1: Pair, 16 bytes, and Particle, 96 bytes, each
+ * sorted by a uint64 key): every record's key is read from key_offset, the
+ * keys are sorted with their input index as payload by the four steps above
+ * (stable: equal keys keep their input order), and the records are copied in
+ * that order. */
+int oracle_sort_records(int dtype, uint64_t n, const void *records, uint32_t record_bytes,
+                        uint32_t key_offset, uint32_t n_b, uint32_t n_p, void *records_out) {
+  const int kb = key_bytes(dtype);
+  if (!kb || record_bytes == 0 || key_offset + (uint32_t)kb > record_bytes || n_b == 0 ||
+      n_p == 0 || n > 0xffffffffull || (n && (!records || !records_out)))
+    return ORACLE_ERR_ARGS;
+  int rc = ORACLE_OK;
+  unsigned char *keys = (unsigned char *)malloc((n ? n : 1) * (size_t)kb);
+  unsigned char *keys_sorted = (unsigned char *)malloc((n ? n : 1) * (size_t)kb);
+  uint32_t *idx = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+  uint32_t *perm = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+  if (!keys || !keys_sorted || !idx || !perm) {
+    rc = ORACLE_ERR_NOMEM;
+    goto done;
+  }
+  idx[0] = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    memcpy(keys + i * kb, (const unsigned char *)records + i * record_bytes + key_offset, kb);
+    idx[i] = (uint32_t)i;
+  }
+  rc = oracle_pses(dtype, n, keys, idx, n_b, n_p, keys_sorted, perm, NULL, NULL, NULL, NULL,
+                   NULL, 0);
+  if (rc) goto done;
+  /* the payload must come back as a permutation of 0..n-1 */
+  memset(idx, 0, (n ? n : 1) * sizeof(uint32_t));
+  for (uint64_t j = 0; j < n; ++j) {
+    if (perm[j] >= n || idx[perm[j]]) {
+      rc = ORACLE_ERR_PERM;
+      goto done;
+    }
+    idx[perm[j]] = 1;
+  }
+  for (uint64_t j = 0; j < n; ++j)
+    memcpy((unsigned char *)records_out + j * record_bytes,
+           (const unsigned char *)records + (uint64_t)perm[j] * record_bytes, record_bytes);
+
+done:
+  free(keys); free(keys_sorted); free(idx); free(perm);
+  return rc;
+}

@@ -34,7 +34,8 @@ enum {
   ORACLE_ERR_SPLIT_MONO = 13, /* s[b][k] > s[b][k+1]                            */
   ORACLE_ERR_OFFSET = 14,     /* O_k != r_k                                     */
   ORACLE_ERR_PART_SIZE = 15,  /* |partition k| not floor or ceil of N/n_P       */
-  ORACLE_ERR_NO_PIVOT = 16    /* r_k > 0 but no block produced a candidate      */
+  ORACLE_ERR_NO_PIVOT = 16,   /* r_k > 0 but no block produced a candidate      */
+  ORACLE_ERR_PERM = 17        /* sorted indices are not a permutation of 0..n-1 */
 };
 
 /* Step O0: three-way comparison of two keys of the given type, given as raw
@@ -85,6 +86,16 @@ int oracle_psrs(int dtype, uint64_t n, const void *keys, const uint32_t *vals,
                 uint32_t *vals_out, void *blocks_out, void *samples_out,
                 uint64_t *n_samples, void *pivots, uint64_t *split,
                 uint64_t *offsets);
+
+/*
+ * Fixed-size records (Table 1's Pair and Particle) sorted by the key of type
+ * dtype at byte offset key_offset of each record_bytes-byte record: the keys
+ * with their input index go through oracle_pses (n_blocks, n_parts), and the
+ * records are copied in the resulting stable order.  n < 2^32.
+ */
+int oracle_sort_records(int dtype, uint64_t n, const void *records, uint32_t record_bytes,
+                        uint32_t key_offset, uint32_t n_blocks, uint32_t n_parts,
+                        void *records_out);
 
 /* Plain counts |{x in keys : x < v}| and |{x in keys : x <= v}| by one linear
  * pass: the definition used by Eq. 1, for checks at sizes where the full

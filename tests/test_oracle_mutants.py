@@ -68,6 +68,12 @@ MUTANTS = {
     "psrs partition by lower bound": (
         "? count_less_equal(dtype, blk[b], blen[b], piv[k]) : 0;",
         "? count_less(dtype, blk[b], blen[b], piv[k]) : 0;"),
+    "records copied in input order": (
+        "(const unsigned char *)records + (uint64_t)perm[j] * record_bytes, record_bytes);",
+        "(const unsigned char *)records + (uint64_t)j * record_bytes, record_bytes);"),
+    "records keyed at offset 0": (
+        "memcpy(keys + i * kb, (const unsigned char *)records + i * record_bytes + key_offset, kb);",
+        "memcpy(keys + i * kb, (const unsigned char *)records + i * record_bytes, kb);"),
     "psrs merge tie to higher block": (
         "rc = merge_selection_tree(dtype, seg, seg_len, n_b, merged + off[k]);\n    if (rc) goto done;\n  }\n\n  for (uint64_t i = 0; i < n; ++i) {\n    store_bits(keys_out, i, kb, merged[i].bits);\n    if (vals) vals_out[i] = merged[i].val;\n  }\n  if (samples_out)",
         "for (uint32_t h = 0; h < n_b / 2; ++h) { const elem_t *t = seg[h]; seg[h] = seg[n_b - 1 - h]; seg[n_b - 1 - h] = t; uint64_t u = seg_len[h]; seg_len[h] = seg_len[n_b - 1 - h]; seg_len[n_b - 1 - h] = u; }\n    rc = merge_selection_tree(dtype, seg, seg_len, n_b, merged + off[k]);\n    if (rc) goto done;\n  }\n\n  for (uint64_t i = 0; i < n; ++i) {\n    store_bits(keys_out, i, kb, merged[i].bits);\n    if (vals) vals_out[i] = merged[i].val;\n  }\n  if (samples_out)"),
@@ -89,9 +95,22 @@ def psrs_pins(lib) -> None:
         assert np.array_equal(r.keys, keys[perm]) and np.array_equal(r.vals, perm)
 
 
+def record_pins(lib) -> None:
+    """Compact record-sort pins: Particle-shaped records with the key at the
+    end, against (key, index) order."""
+    rng = np.random.default_rng(9)
+    for n in (5, 300):
+        rec = rng.integers(0, 256, size=(n, 96), dtype=np.uint8)
+        keys = rng.integers(0, 4, size=n).astype(np.float64)
+        rec[:, 88:96] = keys.view(np.uint8).reshape(n, 8)
+        got = oracle.sort_records(rec, "f64", 88, 3, 3, lib=lib)
+        assert np.array_equal(got, rec[refdefs.stable_order(keys)])
+
+
 def pin_suite(lib) -> None:
     """Compact pins: worked examples, totalOrder table, brute force, closed
     forms and random inputs.  Raises on the first failed pin."""
+    record_pins(lib)
     psrs_pins(lib)
     with open(os.path.join(GOLDEN, "fig1_parallel_sort.json")) as f:
         g1 = json.load(f)

@@ -223,6 +223,61 @@ def bench_splitting(pss, torch, log2n: int, steps: int, warmup: int,
     return res
 
 
+def bench_records(pss, torch, steps: int, warmup: int) -> dict:
+    """Table 1's record workloads sorted by their uint64 key: Pair (16-byte
+    key + index records, 2^27 of them) and Particle (96-byte key + 11 doubles,
+    2^26).  Keys uniform over [0, 2^64) (seed 19); the payload bytes come from
+    torch's device generator seeded with 20.  The output is checked to be
+    ordered by key.  Reported: records/s, record bytes moved (one read and one
+    write of every record) per second, and library time per phase."""
+    import numpy as np
+
+    import workloads as W
+    from paper_2305_05245_amd import _lib
+
+    res = {}
+    for name, rb, log2n in (("pair", 16, 27), ("particle", 96, 26)):
+        n = 1 << log2n
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(20)
+        rec = torch.randint(0, 256, (n, rb), dtype=torch.uint8, device="cuda", generator=gen)
+        keys = torch.from_numpy(W.uniform_u64(n, seed=19).view(np.int64)).cuda()
+        rec.view(torch.int64)[:, 0] = keys
+        del keys
+        out = torch.empty_like(rec)
+        ws = torch.empty(_lib.records_workspace_bytes(_lib.U64, n), dtype=torch.uint8,
+                         device="cuda")
+        for _ in range(warmup):
+            pss.sort_records(rec, "u64", 0, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            pss.sort_records(rec, "u64", 0, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        pss.profile(True)
+        pss.profile_read()
+        pss.sort_records(rec, "u64", 0, out=out, workspace=ws)
+        prof = pss.profile_read()
+        pss.profile(False)
+        k = out.view(torch.int64)[:, 0] ^ (-(2 ** 63))   # u64 order as signed
+        assert bool((k[1:] >= k[:-1]).all()), f"{name} records not ordered by key"
+        sort_ms = sum(v["ms"] for x, v in prof.items() if x not in ("record_keys", "record_gather"))
+        res[name] = {
+            "records": n, "record_bytes": rb, "ms": round(dt * 1e3, 3),
+            "grecords_per_s": round(n / dt / 1e9, 3),
+            "record_gb_per_s": round(2 * n * rb / dt / 1e9, 1),
+            "key_extract_ms": round(prof["record_keys"]["ms"], 4),
+            "key_value_sort_ms": round(sort_ms, 4),
+            "gather_ms": round(prof["record_gather"]["ms"], 4),
+        }
+        del rec, out, ws, k
+        torch.cuda.empty_cache()
+    res["workload"] = ("Pair 2^27 x 16 B and Particle 2^26 x 96 B records, uniform u64 key at "
+                       "offset 0, stable sort by key")
+    return res
+
+
 def bench_batched(pss, torch, steps: int, warmup: int) -> dict:
     """4096 int64 arrays of round(2^U) keys, U ~ Uniform[6, 20] (seed 12), keys
     uniform over the full range (seed 13): the segmented sort replayed from one
@@ -422,7 +477,8 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--no-splitting", action="store_true",
                     help="skip the exact-splitting vs regular-sampling comparison")
-    ap.add_argument("--leg", choices=("batched", "serving", "key_value", "splitting"),
+    ap.add_argument("--no-records", action="store_true", help="skip the Pair / Particle records")
+    ap.add_argument("--leg", choices=("batched", "serving", "key_value", "splitting", "records"),
                     help="run only this leg and print its JSON object (for profiling)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a plain device-to-device copy of the keys (bandwidth and "
@@ -448,6 +504,9 @@ def main() -> int:
     if args.leg == "key_value":
         print(json.dumps(bench_key_value(pss, torch, args.log2n, max(3, args.steps // 2), 1)),
               flush=True)
+        return 0
+    if args.leg == "records":
+        print(json.dumps(bench_records(pss, torch, max(3, args.steps // 2), 1)), flush=True)
         return 0
     if args.leg == "splitting":
         print(json.dumps(bench_splitting(pss, torch, args.log2n, max(3, args.steps // 2), 1)),
@@ -557,6 +616,10 @@ def main() -> int:
         torch.cuda.empty_cache()
         print("[bench] batched segmented sort", file=sys.stderr, flush=True)
         line["batched"] = bench_batched(pss, torch, max(3, args.steps // 2), 1)
+        torch.cuda.empty_cache()
+    if not args.no_records:
+        print("[bench] Pair and Particle records", file=sys.stderr, flush=True)
+        line["records"] = bench_records(pss, torch, max(3, args.steps // 2), 1)
         torch.cuda.empty_cache()
     if not args.no_splitting:
         print("[bench] exact splitting vs regular sampling", file=sys.stderr, flush=True)

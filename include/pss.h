@@ -201,6 +201,28 @@ pss_status pss_psrs_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, 
                               void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Records sorted by a key field (Table 1: Pair, 16-byte key-index records,
+ * and Particle, 96-byte records of a key and particle data, both sorted by
+ * their uint64 key): n records of record_bytes bytes (an array of
+ * structures) are written to records_out in ascending key order, stable
+ * (equal keys keep their input order).  The keys and their input indices go
+ * through the key-value sort (pss_sort with PSS_VAL_U32), then whole records
+ * are gathered in that order: records move once, not once per merge pass.
+ *   key / key_offset: type and byte offset of the key inside each record
+ *     (aligned to the key width).
+ *   record_bytes: a multiple of 4 and of the key width, 4..4096.
+ *   records_in, records_out: DEVICE arrays of n * record_bytes bytes, aligned
+ *     to the key width, not overlapping; records_in is never written.
+ * Workspace: pss_records_workspace_bytes (about 2 (w + 4) n bytes plus the
+ * key-value sort's).  Errors as for pss_sort; n < 2^31.
+ */
+pss_status pss_records_workspace_bytes(const pss_ctx *ctx, pss_key_t key, uint64_t n,
+                                       size_t *bytes);
+pss_status pss_sort_records(pss_ctx *ctx, pss_key_t key, const void *records_in,
+                            void *records_out, uint64_t n, uint32_t record_bytes,
+                            uint32_t key_offset, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Batched segmented sort: sort each segment [seg_offsets[i], seg_offsets[i+1])
  * of one array independently (ascending; key-value sorts stable within the
  * segment), all segments in one fixed sequence of launches with no host round

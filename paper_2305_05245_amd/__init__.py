@@ -9,6 +9,7 @@ current HIP stream; every step of the sort runs in the library's HIP kernels.
     out, _ = pss.sort(keys, n_blocks=64, n_parts=64)   # the paper's single level
     info = pss.splitters(keys, 64, 64)           # steps 1-3 (pivots, c_k, split)
     out, _, sizes = pss.psrs_sort(keys, n_blocks=64, n_parts=64)  # regular-sampling pivots
+    out = pss.sort_records(particles, "u64", key_offset=0)       # records [n, 96] uint8
 """
 from __future__ import annotations
 
@@ -19,7 +20,7 @@ import torch
 from . import _lib
 from ._lib import PssError, Tuning, plan, validate, workspace_bytes  # noqa: F401
 
-__all__ = ["sort", "segmented_sort", "splitters", "psrs_sort", "psrs_splitters", "device_check", "Tuning", "key_type_of", "plan", "workspace_bytes", "PssError",
+__all__ = ["sort", "segmented_sort", "splitters", "psrs_sort", "psrs_splitters", "sort_records", "device_check", "Tuning", "key_type_of", "plan", "workspace_bytes", "PssError",
            "Workspace"]
 
 _DTYPE_KEY = {
@@ -282,3 +283,27 @@ def psrs_splitters(keys: torch.Tensor, n_blocks: int, n_parts: int,
                                  ptr(res["pivots"]), ptr(res["split"]), ptr(res["offsets"]),
                                  ws.data_ptr(), ws.numel(), _stream_handle(dev))
     return res
+
+
+def sort_records(records: torch.Tensor, key_type: str | int, key_offset: int = 0,
+                 out: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    """Sort fixed-size records by a key field, stable.  `records` is a
+    contiguous device tensor whose first dimension indexes the records (e.g. a
+    [n, record_bytes] uint8 tensor, or a structured view of the same bytes);
+    the key of type `key_type` sits at byte `key_offset` of each record.
+    Returns the sorted records (same shape and dtype)."""
+    if not records.is_cuda or not records.is_contiguous() or records.dim() < 1:
+        raise ValueError("records must be a contiguous device tensor, one record per row")
+    kt = _lib.KEY_NAMES[key_type] if isinstance(key_type, str) else int(key_type)
+    n = records.shape[0]
+    rb = records.element_size()
+    for d in records.shape[1:]:
+        rb *= d
+    dev = records.device.index if records.device.index is not None else torch.cuda.current_device()
+    if out is None:
+        out = torch.empty_like(records)
+    need = _lib.records_workspace_bytes(kt, n)
+    ws = workspace if workspace is not None else Workspace.get(dev, need)
+    _context(dev).sort_records(kt, records.data_ptr(), out.data_ptr(), n, rb, key_offset,
+                               ws.data_ptr(), ws.numel(), _stream_handle(dev))
+    return out

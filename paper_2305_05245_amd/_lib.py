@@ -80,6 +80,8 @@ SIGNATURES = {
     "pss_server_destroy": (None, [_vp]),
     "pss_splitters": (_int, [_vp, _int, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                              _vp]),
+    "pss_records_workspace_bytes": (_int, [_vp, _int, _u64, _c.POINTER(_sz)]),
+    "pss_sort_records": (_int, [_vp, _int, _vp, _vp, _u64, _u32, _u32, _vp, _sz, _vp]),
     "pss_psrs_workspace_bytes": (_int, [_vp, _int, _int, _u64, _u32, _u32, _c.POINTER(_sz)]),
     "pss_psrs_sort": (_int, [_vp, _int, _int, _vp, _vp, _vp, _vp, _u64, _u32, _u32, _vp, _vp, _sz,
                              _vp]),
@@ -139,6 +141,12 @@ def validate(key: int, val: int, keys_in: int, keys_out: int, vals_in: int, vals
 def workspace_bytes(key: int, val: int, n: int, n_blocks: int = 0, n_parts: int = 0) -> int:
     out = ctypes.c_size_t()
     check(load().pss_workspace_bytes(None, key, val, n, n_blocks, n_parts, ctypes.byref(out)))
+    return int(out.value)
+
+
+def records_workspace_bytes(key: int, n: int) -> int:
+    out = ctypes.c_size_t()
+    check(load().pss_records_workspace_bytes(None, key, n, ctypes.byref(out)))
     return int(out.value)
 
 
@@ -265,6 +273,13 @@ class Context:
         code = ctypes.c_uint32()
         check(self.lib.pss_device_check(self.handle, ctypes.byref(code)), self.handle)
         return int(code.value)
+
+    def sort_records(self, key: int, records_in: int, records_out: int, n: int,
+                     record_bytes: int, key_offset: int, ws: int, ws_bytes: int,
+                     stream: int) -> None:
+        check(self.lib.pss_sort_records(self.handle, key, records_in or None, records_out or None,
+                                        n, record_bytes, key_offset, ws or None, ws_bytes,
+                                        stream or None), self.handle)
 
     def psrs_sort(self, key: int, val: int, keys_in: int, keys_out: int, vals_in: int,
                   vals_out: int, n: int, n_blocks: int, n_parts: int, part_sizes: int, ws: int,

@@ -494,6 +494,35 @@ pss_status psrs_prepare(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *
   return PSS_OK;
 }
 
+// Workspace of a record sort: keys, indices, sorted keys, permutation, then
+// the key-value sort's own workspace.
+struct RecordPlan {
+  size_t off_keys = 0, off_idx = 0, off_skeys = 0, off_perm = 0, off_sort = 0, total = 0;
+};
+
+pss_status record_plan(const pss_ctx *ctx, pss_key_t key, uint64_t n, RecordPlan *rp) {
+  if ((int)key < 0 || (int)key > 5) return fail(ctx, PSS_ERR_INVALID, "unknown key type");
+  if (n > PSS_MAX_KEYS) return fail(ctx, PSS_ERR_UNSUPPORTED, "n >= 2^31 is not supported");
+  Plan p;
+  std::string err;
+  const pss_status st = make_plan(key, PSS_VAL_U32, n, 0, 0, &p, &err);
+  if (st != PSS_OK) return fail(ctx, st, err);
+  const size_t kb = (size_t)pss::key_bytes((int)key);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  rp->off_keys = take(n * kb);
+  rp->off_idx = take(n * 4);
+  rp->off_skeys = take(n * kb);
+  rp->off_perm = take(n * 4);
+  rp->off_sort = take(p.total);
+  rp->total = off;
+  return PSS_OK;
+}
+
 }  // namespace
 
 namespace pss {
@@ -1041,6 +1070,66 @@ pss_status pss_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, uint6
             "offset copy");
   if (split) PSS_TRY(pss::launch_split_table(p.top, table, split, s), "split table launch");
   if (sorted_blocks) PSS_TRY(pss::launch_unmap_copy(kt, kb[P], sorted_blocks, n, s), "block copy");
+  return PSS_OK;
+}
+
+
+pss_status pss_records_workspace_bytes(const pss_ctx *ctx, pss_key_t key, uint64_t n,
+                                       size_t *bytes) {
+  if (!bytes) return fail(ctx, PSS_ERR_INVALID, "null output pointer");
+  RecordPlan rp;
+  const pss_status st = record_plan(ctx, key, n, &rp);
+  if (st != PSS_OK) return st;
+  *bytes = rp.total;
+  return PSS_OK;
+}
+
+pss_status pss_sort_records(pss_ctx *ctx, pss_key_t key, const void *records_in,
+                            void *records_out, uint64_t n, uint32_t record_bytes,
+                            uint32_t key_offset, void *ws, size_t ws_bytes, void *stream) {
+  if (!ctx) return fail(nullptr, PSS_ERR_INVALID, "null context");
+  RecordPlan rp;
+  pss_status st = record_plan(ctx, key, n, &rp);
+  if (st != PSS_OK) return st;
+  const uint32_t kb = (uint32_t)pss::key_bytes((int)key);
+  if (record_bytes < 4 || record_bytes > 4096 || record_bytes % 4 != 0 || record_bytes % kb != 0)
+    return fail(ctx, PSS_ERR_INVALID,
+                "record_bytes must be a multiple of 4 and of the key width, 4..4096");
+  if (key_offset % kb != 0 || key_offset + kb > record_bytes)
+    return fail(ctx, PSS_ERR_INVALID, "the key must lie aligned inside the record");
+  if (n == 0) return PSS_OK;
+  if (!records_in || !records_out) return fail(ctx, PSS_ERR_INVALID, "null record pointer");
+  if (((uintptr_t)records_in | (uintptr_t)records_out) % kb != 0)
+    return fail(ctx, PSS_ERR_INVALID, "record arrays must be aligned to the key width");
+  if (overlaps(records_in, n * record_bytes, records_out, n * record_bytes))
+    return fail(ctx, PSS_ERR_INVALID, "records_in and records_out overlap");
+  if (!ws) return fail(ctx, PSS_ERR_WORKSPACE, "null workspace");
+  if (ws_bytes < rp.total) {
+    char m[160];
+    snprintf(m, sizeof m, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
+             rp.total);
+    return fail(ctx, PSS_ERR_WORKSPACE, m);
+  }
+  PSS_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  char *w = (char *)ws;
+  void *keys = w + rp.off_keys;
+  uint32_t *idx = (uint32_t *)(w + rp.off_idx);
+  uint32_t *perm = (uint32_t *)(w + rp.off_perm);
+  {
+    LaunchTimer t(ctx, "record_keys", n * ((uint64_t)record_bytes + kb + 4), s);
+    PSS_TRY(pss::launch_record_keys((int)key, records_in, n, record_bytes, key_offset, keys, idx,
+                                    s),
+            "record key launch");
+  }
+  st = pss_sort(ctx, key, PSS_VAL_U32, keys, w + rp.off_skeys, idx, perm, n, 0, 0,
+                w + rp.off_sort, ws_bytes - rp.off_sort, stream);
+  if (st != PSS_OK) return st;
+  {
+    LaunchTimer t(ctx, "record_gather", 2 * n * (uint64_t)record_bytes + 4 * n, s);
+    PSS_TRY(pss::launch_record_gather(records_in, records_out, perm, n, record_bytes, s),
+            "record gather launch");
+  }
   return PSS_OK;
 }
 

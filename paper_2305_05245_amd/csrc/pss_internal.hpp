@@ -184,6 +184,14 @@ hipError_t launch_split_table(const RunGeom &g, const uint32_t *table, uint64_t 
                               hipStream_t s);
 hipError_t launch_unmap_copy(int kt, const void *src, void *dst, uint64_t n, hipStream_t s);
 
+// Records: their keys (raw, of type kt, at key_offset) and input indices;
+// and the gather out[j] = in[perm[j]] of whole records (record_bytes a
+// multiple of 4 and at most 4096).
+hipError_t launch_record_keys(int kt, const void *records, uint64_t n, uint32_t record_bytes,
+                              uint32_t key_offset, void *keys, uint32_t *idx, hipStream_t s);
+hipError_t launch_record_gather(const void *in, void *out, const uint32_t *perm, uint64_t n,
+                                uint32_t record_bytes, hipStream_t s);
+
 // Regular-sampling (PSRS) pivots over the sorted blocks of g (paper mode;
 // blocks hold mapped keys).  samples: n_P - 1 keys from each non-empty block.
 hipError_t launch_psrs_samples(int kt, const void *blocks, const RunGeom &g, void *samples,

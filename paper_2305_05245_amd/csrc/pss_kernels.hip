@@ -2014,6 +2014,34 @@ __global__ void psrs_chunks_kernel(RunGeom g, const uint64_t *__restrict__ bound
   chunks[p] = (m + g.part_len - 1) / g.part_len;
 }
 
+// ------------------------------------------------------------ records ---
+// Fixed-size records sorted by a key field (Table 1's Pair and Particle):
+// the keys and their input indices go through the key-value sort, then the
+// whole records are gathered in the sorted order.
+
+template <typename U>
+__global__ void record_keys_kernel(const unsigned char *__restrict__ rec, uint64_t n, uint32_t rb,
+                                   uint32_t koff, U *__restrict__ keys, uint32_t *__restrict__ idx) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = *reinterpret_cast<const U *>(rec + i * rb + koff);
+  idx[i] = (uint32_t)i;
+}
+
+// Each workgroup copies blockDim / words whole records, one W-sized word per
+// thread: word w of output record j is word w of input record perm[j].
+// Stores are contiguous across the workgroup; loads within a record.
+template <typename W>
+__global__ void record_gather_kernel(const W *__restrict__ in, W *__restrict__ out,
+                                     const uint32_t *__restrict__ perm, uint64_t n,
+                                     uint32_t words) {
+  const uint32_t rpb = blockDim.x / words;
+  const uint32_t r = threadIdx.x / words, w = threadIdx.x - r * words;
+  const uint64_t j = (uint64_t)blockIdx.x * rpb + r;
+  if (r >= rpb || j >= n) return;
+  out[j * words + w] = in[(uint64_t)perm[j] * words + w];
+}
+
 // ------------------------------------------------- segmented planning ---
 // One workgroup reads the segment offsets, checks them, and writes per
 // segment: its tile class and tiles, merge passes, samples, and per pass the
@@ -2442,6 +2470,43 @@ hipError_t launch_psrs_chunks(const RunGeom &g, const uint64_t *bounds, uint64_t
   hipLaunchKernelGGL(exclusive_scan_u64_kernel, dim3(1), dim3(1024), 0, s, (const uint64_t *)chunks,
                      chunk_prefix, (uint64_t)g.n_parts);
   return hipGetLastError();
+}
+
+hipError_t launch_record_keys(int kt, const void *records, uint64_t n, uint32_t record_bytes,
+                              uint32_t key_offset, void *keys, uint32_t *idx, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t grid = (uint32_t)((n + 255) / 256);
+  if (key_bytes(kt) == 8)
+    hipLaunchKernelGGL((record_keys_kernel<uint64_t>), dim3(grid), dim3(256), 0, s,
+                       (const unsigned char *)records, n, record_bytes, key_offset,
+                       (uint64_t *)keys, idx);
+  else
+    hipLaunchKernelGGL((record_keys_kernel<uint32_t>), dim3(grid), dim3(256), 0, s,
+                       (const unsigned char *)records, n, record_bytes, key_offset,
+                       (uint32_t *)keys, idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_record_gather(const void *in, void *out, const uint32_t *perm, uint64_t n,
+                                uint32_t record_bytes, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uintptr_t align = (uintptr_t)in | (uintptr_t)out | record_bytes;
+  auto go = [&](auto w) -> hipError_t {
+    using W = decltype(w);
+    const uint32_t words = record_bytes / (uint32_t)sizeof(W);
+    const uint32_t threads = words <= 256 ? 256 : 1024;
+    if (words > threads) return hipErrorInvalidValue;
+    const uint64_t rpb = threads / words;
+    const uint64_t grid = (n + rpb - 1) / rpb;
+    if (grid > 0x7fffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((record_gather_kernel<W>), dim3((uint32_t)grid), dim3(threads), 0, s,
+                       (const W *)in, (W *)out, perm, n, words);
+    return hipGetLastError();
+  };
+  if (align % 16 == 0) return go(uint4{});
+  if (align % 8 == 0) return go(uint2{});
+  if (align % 4 == 0) return go(uint32_t{});
+  return hipErrorInvalidValue;
 }
 
 hipError_t read_device_error(uint32_t *code, bool clear) {

@@ -278,6 +278,55 @@ def bench_records(pss, torch, steps: int, warmup: int) -> dict:
     return res
 
 
+def bench_paper_inputs(pss, torch, steps: int, warmup: int) -> dict:
+    """The paper's six input sequences (Table 1) at its two sizes, N = 10^7 and
+    10^8, each sorted by the automatic plan on one GPU: UniformInt (uint32,
+    seed 1), UniformFloat (float32 in [0, 1), seed 18), AlmostSorted (0..N-1
+    with sqrt(N) random transpositions, seed 17), Duplicate3 (uint32 in {0, 1,
+    2}, seed 16), Pair (16-byte key + index records) and Particle (96-byte
+    records), both keyed by uniform uint64 (seed 19, payload from torch's
+    device generator, seed 20).  Times in ms per sort."""
+    import numpy as np
+
+    import workloads as W
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    res = {}
+    for n in (10 ** 7, 10 ** 8):
+        row = {}
+        for name, gen, kt in (("UniformInt", W.uniform_u32, "u32"),
+                              ("UniformFloat", W.uniform01_f32, "f32"),
+                              ("AlmostSorted", W.almost_sorted_u32, "u32"),
+                              ("Duplicate3", W.duplicate3_u32, "u32")):
+            keys = torch.from_numpy(gen(n).view(np.int32)).cuda()
+            out = torch.empty_like(keys)
+            dt = timed(lambda: pss.sort(keys, key_type=kt, out=out))
+            row[name] = {"ms": round(dt * 1e3, 3), "gkeys_per_s": round(n / dt / 1e9, 3)}
+            del keys, out
+        for name, rb in (("Pair", 16), ("Particle", 96)):
+            g = torch.Generator(device="cuda")
+            g.manual_seed(20)
+            rec = torch.randint(0, 256, (n, rb), dtype=torch.uint8, device="cuda", generator=g)
+            rec.view(torch.int64)[:, 0] = torch.from_numpy(W.uniform_u64(n, seed=19).view(np.int64)).cuda()
+            out = torch.empty_like(rec)
+            dt = timed(lambda: pss.sort_records(rec, "u64", 0, out=out))
+            row[name] = {"ms": round(dt * 1e3, 3), "gkeys_per_s": round(n / dt / 1e9, 3)}
+            del rec, out
+        torch.cuda.empty_cache()
+        res[f"n={n:.0e}"] = row
+    res["workload"] = "Table 1's six inputs at N = 10^7 and 10^8, automatic plan, one GPU"
+    return res
+
+
 def bench_batched(pss, torch, steps: int, warmup: int) -> dict:
     """4096 int64 arrays of round(2^U) keys, U ~ Uniform[6, 20] (seed 12), keys
     uniform over the full range (seed 13): the segmented sort replayed from one
@@ -478,7 +527,10 @@ def main() -> int:
     ap.add_argument("--no-splitting", action="store_true",
                     help="skip the exact-splitting vs regular-sampling comparison")
     ap.add_argument("--no-records", action="store_true", help="skip the Pair / Particle records")
-    ap.add_argument("--leg", choices=("batched", "serving", "key_value", "splitting", "records"),
+    ap.add_argument("--no-paper-inputs", action="store_true",
+                    help="skip the six inputs of the paper at N = 10^7 and 10^8")
+    ap.add_argument("--leg", choices=("batched", "serving", "key_value", "splitting", "records",
+                                      "paper_inputs"),
                     help="run only this leg and print its JSON object (for profiling)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a plain device-to-device copy of the keys (bandwidth and "
@@ -504,6 +556,9 @@ def main() -> int:
     if args.leg == "key_value":
         print(json.dumps(bench_key_value(pss, torch, args.log2n, max(3, args.steps // 2), 1)),
               flush=True)
+        return 0
+    if args.leg == "paper_inputs":
+        print(json.dumps(bench_paper_inputs(pss, torch, max(3, args.steps // 2), 1)), flush=True)
         return 0
     if args.leg == "records":
         print(json.dumps(bench_records(pss, torch, max(3, args.steps // 2), 1)), flush=True)
@@ -616,6 +671,10 @@ def main() -> int:
         torch.cuda.empty_cache()
         print("[bench] batched segmented sort", file=sys.stderr, flush=True)
         line["batched"] = bench_batched(pss, torch, max(3, args.steps // 2), 1)
+        torch.cuda.empty_cache()
+    if not args.no_paper_inputs:
+        print("[bench] the paper's six inputs", file=sys.stderr, flush=True)
+        line["paper_inputs"] = bench_paper_inputs(pss, torch, max(3, args.steps // 2), 1)
         torch.cuda.empty_cache()
     if not args.no_records:
         print("[bench] Pair and Particle records", file=sys.stderr, flush=True)

@@ -222,3 +222,16 @@ def test_c3_distributions_exact_at_2p22(dist):
     got, _ = gpu_sort(keys)
     exp, _ = oracle_sort(keys)
     assert same_bits(got, exp)
+
+
+@pytest.mark.parametrize("name", ["UniformInt", "UniformFloat", "AlmostSorted", "Duplicate3"])
+def test_paper_inputs_at_1e7(name):
+    """Table 1's four scalar inputs at the paper's N = 10^7, automatic plan,
+    against the oracle run with the paper's 48 blocks and partitions."""
+    gen = {"UniformInt": W.uniform_u32, "UniformFloat": W.uniform01_f32,
+           "AlmostSorted": W.almost_sorted_u32, "Duplicate3": W.duplicate3_u32}[name]
+    keys = gen(10 ** 7)
+    announce("paper input", name, keys.size)
+    got, _ = gpu_sort(keys)
+    ref = oracle.pses(keys, 48, 48)
+    assert same_bits(got, ref.keys)

@@ -360,14 +360,31 @@ pss_status pss_server_reset_stats(pss_server *server);
 void pss_server_destroy(pss_server *server);
 
 /*
+ * How step 4 of the paper's single level (pss_sort with n_blocks > 0, and
+ * pss_psrs_sort) combines the sorted segments of a partition (Section 2.2):
+ *   PSS_MERGE_PAIRWISE (default): stable pairwise merge rounds in LDS, one
+ *     workgroup per chunk of at most 8192 keys;
+ *   PSS_MERGE_SORT: the chunk's segments are gathered and sorted as a whole
+ *     (the paper's "merging by sequential sorting"), with ties broken by
+ *     (block, position), so the output is the same.
+ * A setting of the context; the automatic plan's merge passes always merge.
+ */
+typedef enum { PSS_MERGE_PAIRWISE = 0, PSS_MERGE_SORT = 1 } pss_merge_method;
+pss_status pss_set_merge_method(pss_ctx *ctx, pss_merge_method method);
+
+/*
  * Per-launch timing for measurement.  While enabled, every kernel launch that
  * a call on ctx makes is bracketed by two HIP events recorded on that call's
  * stream (a few microseconds of overhead per launch).  pss_profile_read waits
  * for the recorded events and writes a NUL-terminated JSON object to buf (host
  * memory): {"<kernel family>": {"launches": L, "ms": total milliseconds,
  * "bytes": algorithmic HBM bytes of those launches}, ...}, then forgets the
- * records.  Families: tile_sort (step 1), split_search (steps 2-3), merge
- * (step 4), offset_scan (offsets of the merged partitions).
+ * records.  Families: tile_sort (step 1 tiles), sample_split_search,
+ * sample_merge, split_search and merge (the merge passes: steps 2-4 over
+ * groups of runs), partition_search, offset_scan and partition_merge (steps
+ * 2-4 of the paper's single level), psrs_samples, psrs_sample_sort,
+ * psrs_partition and psrs_chunks (regular-sampling pivots), record_keys and
+ * record_gather (record sorts).
  */
 pss_status pss_profile_enable(pss_ctx *ctx, int on);
 pss_status pss_profile_read(pss_ctx *ctx, char *buf, size_t buf_len);

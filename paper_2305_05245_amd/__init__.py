@@ -20,7 +20,7 @@ import torch
 from . import _lib
 from ._lib import PssError, Tuning, plan, validate, workspace_bytes  # noqa: F401
 
-__all__ = ["sort", "segmented_sort", "splitters", "psrs_sort", "psrs_splitters", "sort_records", "device_check", "Tuning", "key_type_of", "plan", "workspace_bytes", "PssError",
+__all__ = ["sort", "segmented_sort", "splitters", "psrs_sort", "psrs_splitters", "sort_records", "set_merge_method", "device_check", "Tuning", "key_type_of", "plan", "workspace_bytes", "PssError",
            "Workspace"]
 
 _DTYPE_KEY = {
@@ -307,3 +307,12 @@ def sort_records(records: torch.Tensor, key_type: str | int, key_offset: int = 0
     _context(dev).sort_records(kt, records.data_ptr(), out.data_ptr(), n, rb, key_offset,
                                ws.data_ptr(), ws.numel(), _stream_handle(dev))
     return out
+
+
+MERGE_METHODS = {"pairwise": 0, "sort": 1}
+
+
+def set_merge_method(method: str, device: int = 0) -> None:
+    """Step 4 of the paper's single level on `device`: "pairwise" stable merge
+    rounds (default) or "sort" (gather each chunk and sort it, Section 2.2)."""
+    _context(device).set_merge_method(MERGE_METHODS[method])

@@ -80,6 +80,7 @@ SIGNATURES = {
     "pss_server_destroy": (None, [_vp]),
     "pss_splitters": (_int, [_vp, _int, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                              _vp]),
+    "pss_set_merge_method": (_int, [_vp, _int]),
     "pss_records_workspace_bytes": (_int, [_vp, _int, _u64, _c.POINTER(_sz)]),
     "pss_sort_records": (_int, [_vp, _int, _vp, _vp, _u64, _u32, _u32, _vp, _sz, _vp]),
     "pss_psrs_workspace_bytes": (_int, [_vp, _int, _int, _u64, _u32, _u32, _c.POINTER(_sz)]),
@@ -273,6 +274,9 @@ class Context:
         code = ctypes.c_uint32()
         check(self.lib.pss_device_check(self.handle, ctypes.byref(code)), self.handle)
         return int(code.value)
+
+    def set_merge_method(self, method: int) -> None:
+        check(self.lib.pss_set_merge_method(self.handle, method), self.handle)
 
     def sort_records(self, key: int, records_in: int, records_out: int, n: int,
                      record_bytes: int, key_offset: int, ws: int, ws_bytes: int,

@@ -21,6 +21,7 @@ struct pss_ctx {
   int device = 0;
   std::string last_error;
   bool profiling = false;
+  pss_merge_method merge_method = PSS_MERGE_PAIRWISE;
   std::vector<pss_prof_rec> recs;
   std::vector<hipEvent_t> pool;  // events ready for reuse
 };
@@ -462,9 +463,14 @@ pss_status run_psrs(pss_ctx *ctx, const PsrsPlan &pp, int kt, const void *keys_i
   }
   {
     LaunchTimer t(ctx, "partition_merge", 2 * p.n * ((uint64_t)p.kb + (p.kv ? 4 : 0)), s);
-    PSS_TRY(pss::launch_merge(kt, p.kv ? 1 : 0, blocks, vbuf[P], keys_out, vals_out, top, table,
-                              nullptr, 1, nullptr, nullptr, s),
-            "merge launch");
+    if (ctx->merge_method == PSS_MERGE_SORT)
+      PSS_TRY(pss::launch_sort_merge(kt, p.kv, blocks, vbuf[P], keys_out, vals_out, top, table,
+                                     nullptr, 1, s),
+              "merge launch");
+    else
+      PSS_TRY(pss::launch_merge(kt, p.kv ? 1 : 0, blocks, vbuf[P], keys_out, vals_out, top, table,
+                                nullptr, 1, nullptr, nullptr, s),
+              "merge launch");
   }
   return PSS_OK;
 }
@@ -556,6 +562,14 @@ void pss_destroy(pss_ctx *ctx) {
   }
   for (auto e : ctx->pool) hipEventDestroy(e);
   delete ctx;
+}
+
+pss_status pss_set_merge_method(pss_ctx *ctx, pss_merge_method method) {
+  if (!ctx) return fail(nullptr, PSS_ERR_INVALID, "null context");
+  if (method != PSS_MERGE_PAIRWISE && method != PSS_MERGE_SORT)
+    return fail(ctx, PSS_ERR_INVALID, "unknown merge method");
+  ctx->merge_method = method;
+  return PSS_OK;
 }
 
 pss_status pss_profile_enable(pss_ctx *ctx, int on) {
@@ -720,9 +734,14 @@ pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys
     }
     {
       LaunchTimer t(ctx, "partition_merge", sweep, s);
-      PSS_TRY(pss::launch_merge(kt, p.kv ? 1 : 0, kb[P], vb[P], keys_out, vals_out, p.top, table,
-                                offsets, 1, nullptr, nullptr, s),
-              "merge launch");
+      if (ctx->merge_method == PSS_MERGE_SORT)
+        PSS_TRY(pss::launch_sort_merge(kt, p.kv, kb[P], vb[P], keys_out, vals_out, p.top, table,
+                                       offsets, 1, s),
+                "merge launch");
+      else
+        PSS_TRY(pss::launch_merge(kt, p.kv ? 1 : 0, kb[P], vb[P], keys_out, vals_out, p.top,
+                                  table, offsets, 1, nullptr, nullptr, s),
+                "merge launch");
     }
   }
   return PSS_OK;

@@ -184,6 +184,12 @@ hipError_t launch_split_table(const RunGeom &g, const uint32_t *table, uint64_t 
                               hipStream_t s);
 hipError_t launch_unmap_copy(int kt, const void *src, void *dst, uint64_t n, hipStream_t s);
 
+// Step 4 of the paper's single level by sorting each gathered chunk instead
+// of merging its segments (paper-mode geometry only).
+hipError_t launch_sort_merge(int kt, bool kv, const void *src, const uint32_t *vsrc, void *dst,
+                             uint32_t *vdst, const RunGeom &g, const uint32_t *table,
+                             const uint64_t *part_offsets, int final_pass, hipStream_t s);
+
 // Records: their keys (raw, of type kt, at key_offset) and input indices;
 // and the gather out[j] = in[perm[j]] of whole records (record_bytes a
 // multiple of 4 and at most 4096).

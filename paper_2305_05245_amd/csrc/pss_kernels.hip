@@ -1938,6 +1938,108 @@ __global__ void unmap_copy_kernel(const typename Key<KT>::U *__restrict__ src,
   if (i < n) dst[i] = Key<KT>::unmap(src[i]);
 }
 
+// ------------------------------------------------- step 4 by sorting ---
+// Section 2.2's other way to merge: gather the n_B sorted segments of a
+// partition and sort the whole.  One workgroup per chunk of at most kPart
+// keys gathers its segments into LDS in run order, then sorts them with a
+// bitonic network in LDS.  Key-value sorts order (key, LDS position): the
+// position follows (run, position in run), so ties stay stable and the
+// values are read through the sorted positions.
+template <int KT, bool KV>
+__global__ __launch_bounds__(kMergeThreads) void sort_merge_kernel(
+    const typename Key<KT>::U *__restrict__ src, const uint32_t *__restrict__ vsrc,
+    typename Key<KT>::U *__restrict__ dst, uint32_t *__restrict__ vdst, RunGeom g,
+    const uint32_t *__restrict__ table, const uint64_t *__restrict__ part_off, int final_pass) {
+  using U = typename Key<KT>::U;
+  constexpr uint32_t NT = kMergeThreads;
+  constexpr int ITEMS = kPart / NT;
+  __shared__ U sk[kPart];
+  __shared__ uint16_t spos[KV ? kPart : 1];
+  __shared__ uint32_t sv[KV ? kPart : 1];
+  __shared__ uint32_t soff[kMaxRuns + 1];
+  __shared__ uint64_t ssrc[kMaxRuns];
+  __shared__ uint32_t wsum[NT / 64 + 1];
+
+  const uint32_t tid = threadIdx.x;
+  const PartInfo pi = part_info(g, blockIdx.x, table, part_off);
+  if (!pi.valid) return;
+  const uint64_t R = g.run_len;
+  const uint32_t F = (uint32_t)((pi.group_len + R - 1) / R);
+  for (uint32_t b = tid; b < F; b += NT) {
+    const uint32_t lo = pi.lo_row[b], hi = pi.hi_row[b];
+    const uint32_t len = run_length(pi.group_len, R, b);
+    const bool ok = lo <= hi && hi <= len;
+    if (!ok) report(kErrSplitRow);
+    soff[b] = ok ? hi - lo : (uint32_t)kPart + 1;  // forces the size check below to fail
+    ssrc[b] = pi.group_start + (uint64_t)b * R + lo;
+  }
+  __syncthreads();
+  block_exclusive_scan(soff, F, wsum);
+  const uint32_t M = soff[F];
+  if (M != pi.size) {
+    if (tid == 0) report(kErrPartSize);
+    return;
+  }
+  {
+    uint64_t addr[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint32_t idx = i * NT + tid;
+      addr[i] = 0;
+      if (idx < M) {
+        const uint32_t b = find_segment(soff, F, idx);
+        addr[i] = ssrc[b] + (idx - soff[b]);
+      }
+    }
+    U kreg[ITEMS];
+    uint32_t vreg[KV ? ITEMS : 1];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint32_t idx = i * NT + tid;
+      kreg[i] = idx < M ? src[addr[i]] : key_max<U>();
+      if constexpr (KV) vreg[i] = idx < M ? vsrc[addr[i]] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint32_t idx = i * NT + tid;
+      sk[idx] = kreg[i];
+      if constexpr (KV) {
+        spos[idx] = (uint16_t)idx;
+        sv[idx] = vreg[i];
+      }
+    }
+  }
+  __syncthreads();
+  // bitonic sort of all kPart slots (padding holds the largest key at
+  // positions >= M, so it sorts after every real key)
+  for (uint32_t k = 2; k <= (uint32_t)kPart; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t t = tid; t < (uint32_t)kPart / 2; t += NT) {
+        const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+        const uint32_t l = i + j;
+        const U a = sk[i], b = sk[l];
+        bool gt = a > b;
+        if constexpr (KV) gt = gt || (a == b && spos[i] > spos[l]);
+        if (gt == ((i & k) == 0)) {
+          sk[i] = b;
+          sk[l] = a;
+          if constexpr (KV) {
+            const uint16_t pa = spos[i];
+            spos[i] = spos[l];
+            spos[l] = pa;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t idx = tid; idx < M; idx += NT) {
+    const U k = sk[idx];
+    dst[pi.out_off + idx] = final_pass ? Key<KT>::unmap(k) : k;
+    if constexpr (KV) vdst[pi.out_off + idx] = sv[spos[idx]];
+  }
+}
+
 // ------------------------------------------- regular-sampling pivots ---
 // PSRS (Section 2.3): n_P - 1 samples at regular intervals of every sorted
 // block, the samples sorted, n_P - 1 pivots at regular intervals of them, and
@@ -2470,6 +2572,27 @@ hipError_t launch_psrs_chunks(const RunGeom &g, const uint64_t *bounds, uint64_t
   hipLaunchKernelGGL(exclusive_scan_u64_kernel, dim3(1), dim3(1024), 0, s, (const uint64_t *)chunks,
                      chunk_prefix, (uint64_t)g.n_parts);
   return hipGetLastError();
+}
+
+hipError_t launch_sort_merge(int kt, bool kv, const void *src, const uint32_t *vsrc, void *dst,
+                             uint32_t *vdst, const RunGeom &g, const uint32_t *table,
+                             const uint64_t *part_offsets, int final_pass, hipStream_t s) {
+  const uint64_t parts = g.total_parts();
+  if (parts == 0) return hipSuccess;
+  if (!g.paper || g.fan > kMaxRuns) return hipErrorInvalidValue;
+  return dispatch_kt(kt, [&](auto ktc) {
+    constexpr int KT = decltype(ktc)::value;
+    using U = typename Key<KT>::U;
+    if (kv)
+      hipLaunchKernelGGL((sort_merge_kernel<KT, true>), dim3((uint32_t)parts), dim3(kMergeThreads),
+                         0, s, (const U *)src, vsrc, (U *)dst, vdst, g, table, part_offsets,
+                         final_pass);
+    else
+      hipLaunchKernelGGL((sort_merge_kernel<KT, false>), dim3((uint32_t)parts), dim3(kMergeThreads),
+                         0, s, (const U *)src, vsrc, (U *)dst, vdst, g, table, part_offsets,
+                         final_pass);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_record_keys(int kt, const void *records, uint64_t n, uint32_t record_bytes,

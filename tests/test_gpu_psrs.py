@@ -110,3 +110,36 @@ def test_psrs_empty_and_errors():
         pss.psrs_sort(x, n_blocks=0, n_parts=4)
     with pytest.raises(PssError):
         pss.psrs_sort(x, n_blocks=4, n_parts=0)
+
+
+@pytest.mark.parametrize("n,n_b,n_p", [(100003, 7, 13), (50000, 300, 3), (20000, 2048, 5),
+                                       (1 << 18, 100, 7), (5, 4, 9), (1 << 20, 64, 64)])
+@pytest.mark.parametrize("kind", ["uniform", "dup"])
+def test_merge_by_sort(n, n_b, n_p, kind):
+    """Step 4 by sorting each gathered chunk (Section 2.2) gives the same
+    output as the merge, for exact-splitting and regular-sampling pivots,
+    keys only and stable key-value."""
+    import torch
+
+    import paper_2305_05245_amd as pss
+
+    dtype = np.int64 if kind == "uniform" else np.uint32
+    keys = seeded_keys(dtype, n, n + 7 * n_b, kind)
+    vals = np.arange(n, dtype=np.uint32)
+    kt = KEY_OF_DTYPE[keys.dtype]
+    announce("merge by sort", keys.dtype.name, n, n_b, n_p)
+    ref = oracle.pses(keys, n_b, n_p, vals=vals)
+    pss.set_merge_method("sort")
+    try:
+        d, dv = to_device(keys), to_device(vals)
+        k1, _ = pss.sort(d, n_blocks=n_b, n_parts=n_p, key_type=kt)
+        k2, v2 = pss.sort(d, dv, n_blocks=n_b, n_parts=n_p, key_type=kt)
+        k3, v3, _ = pss.psrs_sort(d, dv, n_blocks=n_b, n_parts=n_p, key_type=kt)
+        torch.cuda.synchronize()
+    finally:
+        pss.set_merge_method("pairwise")
+    for k in (k1, k2, k3):
+        assert same_bits(from_device(k, keys.dtype), ref.keys)
+    for v in (v2, v3):
+        assert np.array_equal(from_device(v, np.uint32), ref.vals)
+    assert pss.device_check() == 0

@@ -173,7 +173,8 @@ def _time_split_method(pss, torch, run, steps: int, warmup: int, method: str) ->
 def bench_splitting(pss, torch, log2n: int, steps: int, warmup: int,
                     nbps: tuple = (64, 256)) -> dict:
     """The paper's single level with n_B = n_P = b for each b in nbps, exact
-    splitting (PSES) against regular-sampling pivots (PSRS), on uniform int64
+    splitting (PSES) against regular-sampling pivots (PSRS), and PSES with step
+    4 done by sorting each gathered chunk (Section 2.2), on uniform int64
     keys (seed 2) and Duplicate3 keys {0, 1, 2} as int64 (seed 16): time per
     sort, library time per step (1: block sort; 2-3: pivots and partition
     boundaries, including the co-rank rows that cut partitions into merge
@@ -208,8 +209,14 @@ def bench_splitting(pss, torch, log2n: int, steps: int, warmup: int,
                 return sizes
 
             row = {}
-            for method, run in (("pses", run_pses), ("psrs", run_psrs)):
-                dt, sizes, steps_ms = _time_split_method(pss, torch, run, steps, warmup, method)
+            for method, run in (("pses", run_pses), ("psrs", run_psrs),
+                                ("pses_merge_by_sort", run_pses)):
+                pss.set_merge_method("sort" if method.endswith("by_sort") else "pairwise")
+                try:
+                    dt, sizes, steps_ms = _time_split_method(pss, torch, run, steps, warmup,
+                                                             method.split("_")[0])
+                finally:
+                    pss.set_merge_method("pairwise")
                 sz = sizes if isinstance(sizes, np.ndarray) else sizes.cpu().numpy()
                 row[method] = {
                     "ms": round(dt * 1e3, 3), "gkeys_per_s": round(n / dt / 1e9, 3), **steps_ms,

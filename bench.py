@@ -285,6 +285,58 @@ def bench_records(pss, torch, steps: int, warmup: int) -> dict:
     return res
 
 
+def bench_distributions(pss, torch, steps: int, warmup: int, skip: str = "uniform") -> dict:
+    """The other single-sort configurations, ms per sort: the paper's single
+    level on 2^20 uniform int32 (seed 1) with n_B = n_P = 64; 2^28 int64 in
+    the five distributions (uniform seed 2, mod 1000 seed 3, sorted, reverse,
+    1% transpositions seed 6; `skip` is timed by the main line already); 2^27
+    float64 under totalOrder (uniform [0,1) seed 7, normal seed 8, all 1.0,
+    organ pipe, normal with 0.1% -0.0/+inf/NaN seed 11)."""
+    import numpy as np
+
+    import workloads as W
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    res = {}
+    keys = torch.from_numpy(W.uniform_i32(1 << 20, seed=1)).cuda()
+    out = torch.empty_like(keys)
+    dt = timed(lambda: pss.sort(keys, n_blocks=64, n_parts=64, out=out))
+    res["int32_2p20_paper_64x64"] = {"ms": round(dt * 1e3, 4), "gkeys_per_s": round((1 << 20) / dt / 1e9, 3)}
+    n = 1 << 28
+    keys = torch.empty(n, dtype=torch.int64, device="cuda")
+    out = torch.empty_like(keys)
+    for name, g in generators().items():
+        if name == skip:
+            continue
+        keys.copy_(torch.from_numpy(g(n)))
+        dt = timed(lambda: pss.sort(keys, out=out))
+        res[f"int64_2p28_{name}"] = {"ms": round(dt * 1e3, 3), "gkeys_per_s": round(n / dt / 1e9, 3)}
+    del keys, out
+    n = 1 << 27
+    keys = torch.empty(n, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(keys)
+    for name, g in (("uniform01", lambda: W.uniform01_f64(n, seed=7)),
+                    ("normal", lambda: W.normal_f64(n, seed=8)),
+                    ("allequal", lambda: W.allequal_f64(n)),
+                    ("organpipe", lambda: W.organpipe_f64(n)),
+                    ("normal_specials", lambda: W.normal_specials_f64(n, seed=11))):
+        keys.copy_(torch.from_numpy(g()))
+        dt = timed(lambda: pss.sort(keys, out=out))
+        res[f"float64_2p27_{name}"] = {"ms": round(dt * 1e3, 3), "gkeys_per_s": round(n / dt / 1e9, 3)}
+    del keys, out
+    assert pss.device_check(0) == 0
+    return res
+
+
 def bench_paper_inputs(pss, torch, steps: int, warmup: int) -> dict:
     """The paper's six input sequences (Table 1) at its two sizes, N = 10^7 and
     10^8, each sorted by the automatic plan on one GPU: UniformInt (uint32,
@@ -534,10 +586,12 @@ def main() -> int:
     ap.add_argument("--no-splitting", action="store_true",
                     help="skip the exact-splitting vs regular-sampling comparison")
     ap.add_argument("--no-records", action="store_true", help="skip the Pair / Particle records")
+    ap.add_argument("--no-distributions", action="store_true",
+                    help="skip the other distributions and key types of the single sort")
     ap.add_argument("--no-paper-inputs", action="store_true",
                     help="skip the six inputs of the paper at N = 10^7 and 10^8")
     ap.add_argument("--leg", choices=("batched", "serving", "key_value", "splitting", "records",
-                                      "paper_inputs"),
+                                      "paper_inputs", "distributions"),
                     help="run only this leg and print its JSON object (for profiling)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a plain device-to-device copy of the keys (bandwidth and "
@@ -562,6 +616,10 @@ def main() -> int:
 
     if args.leg == "key_value":
         print(json.dumps(bench_key_value(pss, torch, args.log2n, max(3, args.steps // 2), 1)),
+              flush=True)
+        return 0
+    if args.leg == "distributions":
+        print(json.dumps(bench_distributions(pss, torch, max(3, args.steps // 2), 1, skip="")),
               flush=True)
         return 0
     if args.leg == "paper_inputs":
@@ -678,6 +736,11 @@ def main() -> int:
         torch.cuda.empty_cache()
         print("[bench] batched segmented sort", file=sys.stderr, flush=True)
         line["batched"] = bench_batched(pss, torch, max(3, args.steps // 2), 1)
+        torch.cuda.empty_cache()
+    if not args.no_distributions and not args.all_dists:
+        print("[bench] other distributions and key types", file=sys.stderr, flush=True)
+        line["distributions"] = bench_distributions(pss, torch, max(3, args.steps // 2), 1,
+                                                    skip=args.dist)
         torch.cuda.empty_cache()
     if not args.no_paper_inputs:
         print("[bench] the paper's six inputs", file=sys.stderr, flush=True)

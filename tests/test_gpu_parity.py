@@ -235,3 +235,38 @@ def test_paper_inputs_at_1e7(name):
     got, _ = gpu_sort(keys)
     ref = oracle.pses(keys, 48, 48)
     assert same_bits(got, ref.keys)
+
+
+def test_maximum_size_u32():
+    """The largest supported n, 2^31 - 1 uint32 keys (seed 21), automatic
+    plan (four merge passes): ascending and the same multiset, checked on the
+    device, and sampled ranks by the oracle's direct count on the host."""
+    import torch
+
+    import paper_2305_05245_amd as pss
+
+    n = (1 << 31) - 1
+    keys = W.uniform_u32(n, seed=21)
+    announce("maximum size", n)
+    d = torch.from_numpy(keys.view(np.int32)).cuda()
+    out, _ = pss.sort(d, key_type="u32")
+    torch.cuda.synchronize()
+    assert pss.device_check() == 0
+
+    def signature(t):
+        x = t.to(torch.int64) & 0xFFFFFFFF
+        m1 = (x ^ (x >> 17)) * (0x9E3779B97F4A7C15 - (1 << 64))
+        m1 = m1 ^ (m1 >> 29)
+        m2 = (x + 0x632BE59BD9B4E019) * (0xBF58476D1CE4E5B9 - (1 << 64))
+        m2 = m2 ^ (m2 >> 32)
+        return int(m1.sum()), int(m2.sum())
+
+    x = out.to(torch.int64) & 0xFFFFFFFF
+    assert bool((x[1:] >= x[:-1]).all()), "not ascending"
+    del x
+    assert signature(out) == signature(d), "not a permutation"
+    rng = np.random.default_rng(21)
+    for r in rng.integers(0, n, size=2).tolist() + [0, n - 1]:
+        v = np.uint32(int(out[r].item()) & 0xFFFFFFFF)
+        lt, le = oracle.rank_counts(keys, v)
+        assert lt <= r < le, f"rank {r} holds the wrong key"

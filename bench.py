@@ -147,8 +147,14 @@ def bench_key_value(pss, torch, log2n: int, steps: int, warmup: int) -> dict:
         pss.sort(keys, vals, key_type="u64", out=ko, vals_out=vo, workspace=ws)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    pss.profile(True)
+    pss.profile_read()
+    pss.sort(keys, vals, key_type="u64", out=ko, vals_out=vo, workspace=ws)
+    prof = pss.profile_read()
+    pss.profile(False)
     return {"workload": f"2^{log2n} uniform u64 keys + u32 index values, stable",
-            "ms": round(dt * 1e3, 3), "gkeys_per_s": round(n / dt / 1e9, 3)}
+            "ms": round(dt * 1e3, 3), "gkeys_per_s": round(n / dt / 1e9, 3),
+            "kernels_ms": {k: round(v["ms"], 4) for k, v in prof.items()}}
 
 
 STEP1 = ("tile_sort", "sample_split_search", "sample_merge", "split_search", "merge")

@@ -617,7 +617,7 @@ def main() -> int:
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU path is a design, not part of this build)", file=sys.stderr)
+              "(sharding across GPUs is described in the design notes, not implemented)", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -64,7 +64,7 @@ typedef enum {
 typedef enum {
   PSS_OK = 0,
   PSS_ERR_INVALID = 1,     /* bad argument (null pointer, overlap, bad enum)  */
-  PSS_ERR_UNSUPPORTED = 2, /* valid request outside this build's limits       */
+  PSS_ERR_UNSUPPORTED = 2, /* valid request outside the library's limits      */
   PSS_ERR_OOM = 3,         /* host allocation failed                          */
   PSS_ERR_HIP = 4,         /* a HIP runtime call failed (see pss_last_error)  */
   PSS_ERR_WORKSPACE = 5,   /* workspace missing or smaller than required      */
@@ -75,7 +75,7 @@ typedef enum {
 
 typedef struct pss_ctx pss_ctx;
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define PSS_MAX_KEYS ((uint64_t)2147483647u) /* n < 2^31                      */
 #define PSS_MAX_BLOCKS 2048u                 /* explicit n_B                  */
 #define PSS_MAX_PARTS 4194304u               /* explicit n_P                  */

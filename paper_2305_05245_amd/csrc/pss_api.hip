@@ -45,7 +45,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
-// Largest table (rows x fan entries of uint32) this build allocates.
+// Largest table (rows x fan entries of uint32) the library allocates.
 constexpr uint64_t kMaxTableEntries = (uint64_t)1 << 28;
 
 // Merge passes that sort every segment of seg_len keys, starting from sorted
@@ -126,7 +126,7 @@ pss_status make_plan(pss_key_t key, pss_val_t val, uint64_t n, uint32_t n_blocks
     t.rows_per_group = 0;
     const uint64_t entries = t.total_rows() * (uint64_t)t.fan;
     if (entries > kMaxTableEntries) {
-      *err = "n_blocks * n_parts too large for the split table of this build";
+      *err = "n_blocks * n_parts too large for the library's split table";
       return PSS_ERR_UNSUPPORTED;
     }
     p->table_entries = entries;
@@ -359,7 +359,7 @@ pss_status make_psrs_plan(pss_key_t key, pss_val_t val, uint64_t n, uint32_t n_b
   t.chunk_bound = ceil_div(n, pss::kPart) + n_parts;
   const uint64_t entries = (t.chunk_bound + 1) * (uint64_t)t.fan;
   if (entries > kMaxTableEntries) {
-    *err = "n_blocks * (n / 8192 + n_parts) too large for the split table of this build";
+    *err = "n_blocks * (n / 8192 + n_parts) too large for the library's split table";
     return PSS_ERR_UNSUPPORTED;
   }
   pp->skt = pss::key_bytes((int)key) == 8 ? PSS_U64 : PSS_U32;

@@ -158,9 +158,10 @@ def bench_key_value(pss, torch, log2n: int, steps: int, warmup: int) -> dict:
 
 
 STEP1 = ("tile_sort", "sample_split_search", "sample_merge", "split_search", "merge")
-PIVOTS = {"pses": ("partition_search", "offset_scan"),
+PIVOTS = {"pses": ("partition_sample_search", "partition_sample_merge", "partition_search",
+                   "offset_scan"),
           "psrs": ("psrs_samples", "psrs_sample_sort", "psrs_partition", "psrs_chunks",
-                   "partition_search")}
+                   "partition_sample_search", "partition_sample_merge", "partition_search")}
 
 
 def _time_split_method(pss, torch, run, steps: int, warmup: int, method: str) -> tuple:

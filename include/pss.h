@@ -382,7 +382,9 @@ pss_status pss_set_merge_method(pss_ctx *ctx, pss_merge_method method);
  * records.  Families: tile_sort (step 1 tiles), sample_split_search,
  * sample_merge, split_search and merge (the merge passes: steps 2-4 over
  * groups of runs), partition_search, offset_scan and partition_merge (steps
- * 2-4 of the paper's single level), psrs_samples, psrs_sample_sort,
+ * 2-4 of the paper's single level, with partition_sample_search and
+ * partition_sample_merge when its search starts from the blocks' samples),
+ * psrs_samples, psrs_sample_sort,
  * psrs_partition and psrs_chunks (regular-sampling pivots), record_keys and
  * record_gather (record sorts).
  */

@@ -88,6 +88,11 @@ struct Plan {
   uint64_t seg_len = 0;               // segment sorted by tile sort + passes
   std::vector<pss::RunGeom> passes;   // merge passes inside each segment
   pss::RunGeom top{};                 // paper mode: the cross-block merge
+  // paper mode with at most kMaxSampledFan blocks longer than a tile: the
+  // last block pass leaves every kSample-th key of each block, and the
+  // partition search starts from their merge (geometry top_gs)
+  bool top_sampled = false;
+  pss::RunGeom top_gs{};
   uint64_t table_entries = 0;
   // merged-sample index used by the splitter search of every segment pass
   uint64_t n_samples = 0, sample_table_entries = 0, prefix_entries = 0;
@@ -130,6 +135,28 @@ pss_status make_plan(pss_key_t key, pss_val_t val, uint64_t n, uint32_t n_blocks
       return PSS_ERR_UNSUPPORTED;
     }
     p->table_entries = entries;
+    if (!p->passes.empty() && n_blocks <= pss::kMaxSampledFan) {
+      // blocks' samples as one group of n_blocks runs of L / kSample samples
+      // (the last non-empty block's share is its own length / kSample)
+      pss::RunGeom &gs = p->top_gs;
+      const uint64_t rs = L >> pss::kSampleLog2;
+      const uint64_t nonempty = ceil_div(n, L);
+      const uint64_t last = n - (nonempty - 1) * L;
+      gs.n = (nonempty - 1) * rs + (last >> pss::kSampleLog2);
+      gs.seg_len = gs.n;
+      gs.run_len = rs;
+      gs.fan = n_blocks;
+      gs.group_len = gs.n;
+      gs.groups_per_seg = 1;
+      gs.n_groups = 1;
+      gs.part_len = pss::kPart;
+      gs.rows_per_group = (uint32_t)ceil_div(gs.n, pss::kPart) + 1;
+      gs.paper = 0;
+      p->top_sampled = true;
+      p->n_samples = std::max<uint64_t>(p->n_samples, gs.n);
+      p->sample_table_entries = gs.total_rows() * (uint64_t)gs.fan;
+      p->prefix_entries = gs.total_parts() * (uint64_t)(pss::kPart / pss::kChunk) * gs.fan;
+    }
   }
   for (const auto &g : p->passes) {
     p->table_entries = std::max<uint64_t>(p->table_entries, g.total_rows() * (uint64_t)g.fan);
@@ -260,9 +287,12 @@ struct LaunchTimer {
 // merges the regular samples its input runs left (a 1/kSample-size merge that
 // records run ids and per-run prefix counts), then searches the exact
 // splitters starting from those samples, then merges the data.
+// last_samples: when set, the last pass also leaves every kSample-th key of
+// each output run there (for a search over the sorted segments that follows).
 pss_status run_segment_sort(pss_ctx *ctx, const Plan &p, int kt, const void *keys_in,
                             const uint32_t *vals_in, void *const *kbuf, uint32_t *const *vbuf,
-                            int final_last, char *w, hipStream_t s) {
+                            int final_last, char *w, hipStream_t s,
+                            void *last_samples = nullptr) {
   const size_t P = p.passes.size();
   const uint64_t sweep = 2 * p.n * ((uint64_t)p.kb + (p.kv ? 4 : 0));  // read + write all
   uint32_t *table = (uint32_t *)(w + p.off_table);
@@ -300,10 +330,58 @@ pss_status run_segment_sort(pss_ctx *ctx, const Plan &p, int kt, const void *key
     {
       LaunchTimer t(ctx, "merge", sweep, s);
       PSS_TRY(pss::launch_merge(kt, p.kv ? 1 : 0, kbuf[q - 1], vbuf[q - 1], kbuf[q], vbuf[q], g,
-                                table, nullptr, final_last && q == P, q < P ? samples : nullptr,
-                                nullptr, s),
+                                table, nullptr, final_last && q == P,
+                                q < P ? samples : last_samples, nullptr, s),
               "merge launch");
     }
+  }
+  return PSS_OK;
+}
+
+// Step 1 of the paper's single level (the blocks sorted into kbuf[P], which
+// the caller lays out), leaving the blocks' samples when the partition search
+// will start from them.
+pss_status run_paper_blocks(pss_ctx *ctx, const Plan &p, int kt, const void *keys_in,
+                            const uint32_t *vals_in, void *const *kbuf, uint32_t *const *vbuf,
+                            char *w, hipStream_t s) {
+  return run_segment_sort(ctx, p, kt, keys_in, vals_in, kbuf, vbuf, 0, w, s,
+                          p.top_sampled ? (void *)(w + p.off_samples) : nullptr);
+}
+
+// Steps 2-3 of the paper's single level: co-rank rows of geometry top (the
+// paper's partitions, or data-dependent ones) over the sorted blocks.  With
+// the blocks' samples the search starts at level kSampleLog2 from their merge
+// (sample co-rank, sample merge with run ids and prefix counts); otherwise it
+// runs every level.
+pss_status paper_partition_search(pss_ctx *ctx, const Plan &p, int kt, const void *blocks,
+                                  const pss::RunGeom &top, uint32_t *table, char *w,
+                                  hipStream_t s) {
+  if (!p.top_sampled) {
+    LaunchTimer t(ctx, "partition_search", top.total_rows() * top.fan * 4, s);
+    PSS_TRY(pss::launch_corank(kt, blocks, top, table, nullptr, nullptr, s), "splitter launch");
+    return PSS_OK;
+  }
+  const pss::RunGeom &gs = p.top_gs;
+  void *samples = w + p.off_samples;
+  void *skeys = w + p.off_skeys;
+  uint32_t *sruns = (uint32_t *)(w + p.off_sruns);
+  uint32_t *stable = (uint32_t *)(w + p.off_stable);
+  uint32_t *prefix = (uint32_t *)(w + p.off_prefix);
+  {
+    LaunchTimer t(ctx, "partition_sample_search", gs.total_rows() * gs.fan * 4, s);
+    PSS_TRY(pss::launch_corank(kt, samples, gs, stable, nullptr, nullptr, s),
+            "sample split search launch");
+  }
+  {
+    LaunchTimer t(ctx, "partition_sample_merge", 2 * gs.n * (uint64_t)p.kb + gs.n * 4, s);
+    PSS_TRY(pss::launch_merge(kt, 2, samples, nullptr, skeys, sruns, gs, stable, nullptr, 0,
+                              nullptr, prefix, s),
+            "sample merge launch");
+  }
+  {
+    LaunchTimer t(ctx, "partition_search", top.total_rows() * top.fan * 4, s);
+    PSS_TRY(pss::launch_corank_sampled(kt, blocks, top, table, sruns, prefix, s, nullptr, &gs),
+            "splitter launch");
   }
   return PSS_OK;
 }
@@ -409,7 +487,7 @@ pss_status run_psrs(pss_ctx *ctx, const PsrsPlan &pp, int kt, const void *keys_i
     kbuf[q] = even ? (void *)(w + p.off_keys0) : (void *)(w + p.off_keys1);
     if (p.kv) vbuf[q] = even ? (uint32_t *)(w + p.off_vals0) : (uint32_t *)(w + p.off_vals1);
   }
-  pss_status st = run_segment_sort(ctx, p, kt, keys_in, vals_in, kbuf.data(), vbuf.data(), 0, w, s);
+  pss_status st = run_paper_blocks(ctx, p, kt, keys_in, vals_in, kbuf.data(), vbuf.data(), w, s);
   if (st != PSS_OK) return st;
   const void *blocks = kbuf[P];
   const size_t kbytes = (size_t)p.kb;
@@ -457,10 +535,8 @@ pss_status run_psrs(pss_ctx *ctx, const PsrsPlan &pp, int kt, const void *keys_i
   top.bounds = bounds;
   top.chunk_prefix = cprefix;
   uint32_t *table = (uint32_t *)(w + pp.off_table);
-  {
-    LaunchTimer t(ctx, "partition_search", top.total_rows() * top.fan * 4, s);
-    PSS_TRY(pss::launch_corank(kt, blocks, top, table, nullptr, nullptr, s), "chunk split launch");
-  }
+  st = paper_partition_search(ctx, p, kt, blocks, top, table, w, s);
+  if (st != PSS_OK) return st;
   {
     LaunchTimer t(ctx, "partition_merge", 2 * p.n * ((uint64_t)p.kb + (p.kv ? 4 : 0)), s);
     if (ctx->merge_method == PSS_MERGE_SORT)
@@ -719,15 +795,13 @@ pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys
       kb[q] = even ? (void *)(w + p.off_keys0) : (void *)(w + p.off_keys1);
       if (p.kv) vb[q] = even ? (uint32_t *)(w + p.off_vals0) : (uint32_t *)(w + p.off_vals1);
     }
-    st = run_segment_sort(ctx, p, kt, keys_in, vals_in, kb.data(), vb.data(), 0, w, s);
+    st = run_paper_blocks(ctx, p, kt, keys_in, vals_in, kb.data(), vb.data(), w, s);
     if (st != PSS_OK) return st;
     uint64_t *sizes = (uint64_t *)(w + p.off_sizes);
     uint64_t *offsets = (uint64_t *)(w + p.off_offsets);
     const uint64_t sweep = 2 * p.n * ((uint64_t)p.kb + (p.kv ? 4 : 0));
-    {
-      LaunchTimer t(ctx, "partition_search", p.top.total_rows() * p.top.fan * 4, s);
-      PSS_TRY(pss::launch_corank(kt, kb[P], p.top, table, nullptr, nullptr, s), "splitter launch");
-    }
+    st = paper_partition_search(ctx, p, kt, kb[P], p.top, table, w, s);
+    if (st != PSS_OK) return st;
     {
       LaunchTimer t(ctx, "offset_scan", (uint64_t)p.top.n_parts * 16, s);
       PSS_TRY(pss::launch_partition_offsets(p.top, table, sizes, offsets, s), "offset scan launch");

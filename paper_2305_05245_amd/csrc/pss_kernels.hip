@@ -2440,19 +2440,24 @@ hipError_t launch_corank_sampled(int kt, const void *src, const RunGeom &g, uint
                                  hipStream_t s, const void *src_alt, const RunGeom *gs_in) {
   const uint64_t rows = g.total_rows();
   if (rows == 0) return hipSuccess;
-  if (g.fan > kMaxSampledFan || g.paper) return hipErrorInvalidValue;
+  if (g.fan > kMaxSampledFan) return hipErrorInvalidValue;
+  // the paper's single level has no uniform sample geometry of its own
+  if (g.paper && !gs_in) return hipErrorInvalidValue;
   if (!src_alt) src_alt = src;
   const SampleIndex si{sample_runs, sample_prefix, gs_in ? *gs_in : sample_geom(g)};
-  if (key_bytes(kt) == 8)
-    // at most 32 runs: fewer than 96 candidates a level, two slots a lane
-    hipLaunchKernelGGL((corank_wave_kernel<uint64_t, 2, true>), dim3((uint32_t)rows),
-                       dim3(kCorankThreads), 0, s, (const uint64_t *)src, (const uint64_t *)src_alt,
-                       g, table, (uint64_t *)nullptr, (uint64_t *)nullptr, kt, si);
-  else
-    hipLaunchKernelGGL((corank_wave_kernel<uint32_t, 2, true>), dim3((uint32_t)rows),
-                       dim3(kCorankThreads), 0, s, (const uint32_t *)src, (const uint32_t *)src_alt,
-                       g, table, (uint32_t *)nullptr, (uint64_t *)nullptr, kt, si);
-  return hipGetLastError();
+  // fewer than 3 * fan candidates a level: two slots a lane up to 32 runs
+  auto wave = [&](auto u, auto e) -> hipError_t {
+    using U = decltype(u);
+    hipLaunchKernelGGL((corank_wave_kernel<U, decltype(e)::value, true>), dim3((uint32_t)rows),
+                       dim3(kCorankThreads), 0, s, (const U *)src, (const U *)src_alt, g, table,
+                       (U *)nullptr, (uint64_t *)nullptr, kt, si);
+    return hipGetLastError();
+  };
+  using E2 = std::integral_constant<int, 2>;
+  using E4 = std::integral_constant<int, 4>;
+  const bool wide = key_bytes(kt) == 8;
+  if (g.fan <= 32) return wide ? wave(uint64_t{}, E2{}) : wave(uint32_t{}, E2{});
+  return wide ? wave(uint64_t{}, E4{}) : wave(uint32_t{}, E4{});
 }
 
 hipError_t launch_merge(int kt, int vmode, const void *src, const uint32_t *vsrc, void *dst,

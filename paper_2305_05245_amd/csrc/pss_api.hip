@@ -88,7 +88,7 @@ struct Plan {
   uint64_t seg_len = 0;               // segment sorted by tile sort + passes
   std::vector<pss::RunGeom> passes;   // merge passes inside each segment
   pss::RunGeom top{};                 // paper mode: the cross-block merge
-  // paper mode with at most kMaxSampledFan blocks longer than a tile: the
+  // paper mode with at most kMaxSampledFan blocks of at least 2^16 keys: the
   // last block pass leaves every kSample-th key of each block, and the
   // partition search starts from their merge (geometry top_gs)
   bool top_sampled = false;
@@ -135,7 +135,9 @@ pss_status make_plan(pss_key_t key, pss_val_t val, uint64_t n, uint32_t n_blocks
       return PSS_ERR_UNSUPPORTED;
     }
     p->table_entries = entries;
-    if (!p->passes.empty() && n_blocks <= pss::kMaxSampledFan) {
+    // (blocks shorter than 2^16 keys leave too few levels to skip to pay for
+    // the two extra launches)
+    if (!p->passes.empty() && n_blocks <= pss::kMaxSampledFan && L >= ((uint64_t)1 << 16)) {
       // blocks' samples as one group of n_blocks runs of L / kSample samples
       // (the last non-empty block's share is its own length / kSample)
       pss::RunGeom &gs = p->top_gs;

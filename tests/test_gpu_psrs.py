@@ -143,3 +143,32 @@ def test_merge_by_sort(n, n_b, n_p, kind):
     for v in (v2, v3):
         assert np.array_equal(from_device(v, np.uint32), ref.vals)
     assert pss.device_check() == 0
+
+
+@pytest.mark.parametrize("n,n_b,n_p", [(1 << 22, 16, 16), ((1 << 22) + 12345, 37, 29),
+                                       (1 << 23, 64, 64), ((1 << 21) + 7, 5, 100)])
+@pytest.mark.parametrize("kind", ["uniform", "dup"])
+def test_single_level_sampled_search(n, n_b, n_p, kind):
+    """At most 64 blocks of at least 2^16 keys: the partition search of the
+    single level starts from the blocks' merged samples (block lengths that
+    are not multiples of the sample stride included).  Sorted output (PSES and
+    PSRS, keys only and stable key-value) against the oracle; pss_splitters
+    keeps the full search, so its intermediates check that path too."""
+    import torch
+
+    import paper_2305_05245_amd as pss
+    from test_gpu_parity import check_paper
+
+    dtype = np.int64 if kind == "uniform" else np.uint32
+    keys = seeded_keys(dtype, n, n + 3 * n_b, kind)
+    check_paper(keys, n_b, n_p)
+    vals = np.arange(n, dtype=np.uint32)
+    kt = KEY_OF_DTYPE[keys.dtype]
+    announce("sampled single level kv", n, n_b, n_p)
+    ref = oracle.pses(keys, n_b, n_p, vals=vals)
+    d, dv = to_device(keys), to_device(vals)
+    k1, v1 = pss.sort(d, dv, n_blocks=n_b, n_parts=n_p, key_type=kt)
+    torch.cuda.synchronize()
+    assert same_bits(from_device(k1, keys.dtype), ref.keys)
+    assert np.array_equal(from_device(v1, np.uint32), ref.vals)
+    check_psrs(keys, n_b, n_p, vals=vals)

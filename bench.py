@@ -84,6 +84,9 @@ def measured_traffic(kernel: str, log2n: int, dist: str):
 
 
 def time_sort(pss, torch, keys_dev, out, ws, steps: int, warmup: int, profile: bool):
+    """Wall time of `steps` sorts, their HIP-event time, per-sort event times
+    (events recorded between sorts on the sorting stream) and, with
+    `profile`, the library's per-kernel-family times."""
     for _ in range(warmup):
         pss.sort(keys_dev, out=out, workspace=ws)
     torch.cuda.synchronize()
@@ -91,21 +94,21 @@ def time_sort(pss, torch, keys_dev, out, ws, steps: int, warmup: int, profile: b
         pss.profile(True)
         pss.profile_read()  # drop anything recorded so far
     stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(steps):
+    evs[0].record(stream)
+    for i in range(steps):
         pss.sort(keys_dev, out=out, workspace=ws)
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kernels = None
     if profile:
         kernels = pss.profile_read()
         pss.profile(False)
-    return wall, ev0.elapsed_time(ev1) / 1e3, kernels
+    per_step = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+    return wall, evs[0].elapsed_time(evs[-1]) / 1e3, kernels, per_step
 
 
 def cpu_baseline(log2n: int = 25):
@@ -683,8 +686,8 @@ def main() -> int:
                           "copy_ms": round(copy_s * 1e3, 4), "copy_gbs": round(copy_gbs, 1)}))
         return 0
 
-    wall, ev_s, kernels = time_sort(pss, torch, keys_dev, out, ws, args.steps, args.warmup,
-                                    profile=True)
+    wall, ev_s, kernels, per_step = time_sort(pss, torch, keys_dev, out, ws, args.steps,
+                                              args.warmup, profile=True)
     assert pss.device_check(0) == 0
     ms_per_step = wall / args.steps * 1e3
     gkeys = n / (wall / args.steps) / 1e9
@@ -730,6 +733,9 @@ def main() -> int:
         "roofline": roofline,
         "sort_roofline_2pass_frac": round(algo_bytes / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
         "hip_event_ms_per_step": round(ev_s / args.steps * 1e3, 4),
+        "step_ms": {"mean": round(float(np.mean(per_step)), 4),
+                    "median": round(float(np.median(per_step)), 4),
+                    "min": round(float(np.min(per_step)), 4)},
         "copy_gbs": round(copy_gbs, 1),
         "kernels": {k: {"launches": v["launches"] // args.steps,
                         "ms_per_step": round(v["ms"] / args.steps, 4)} for k, v in kernels.items()},
@@ -743,7 +749,7 @@ def main() -> int:
             k = g(n)
             keys_dev.copy_(torch.from_numpy(k))
             del k
-            w, _, _ = time_sort(pss, torch, keys_dev, out, ws, max(3, args.steps // 2), 1, False)
+            w, _, _, _ = time_sort(pss, torch, keys_dev, out, ws, max(3, args.steps // 2), 1, False)
             per[name] = round(n / (w / max(3, args.steps // 2)) / 1e9, 3)
         line["distributions_gkeys_per_s"] = per
     del keys, keys_dev, out, ws

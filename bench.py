@@ -111,7 +111,7 @@ def time_sort(pss, torch, keys_dev, out, ws, steps: int, warmup: int, profile: b
     return wall, evs[0].elapsed_time(evs[-1]) / 1e3, kernels, per_step
 
 
-def cpu_baseline(log2n: int = 25):
+def cpu_baseline(log2n: int = 26):
     """The oracle as it stands (sequential C, one thread) on a bounded sample
     of the same workload: 2^log2n uniform int64 keys, n_B = n_P = 48."""
     import oracle

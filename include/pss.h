@@ -321,8 +321,9 @@ void pss_graph_destroy(pss_graph *graph);
  * with PSS_ERR_CANCELLED) and returns PSS_ERR_BUSY for one already launched
  * or finished.  pss_server_stats reports counters and, over requests
  * completed since creation or the last pss_server_reset_stats, the latency
- * (arrival to completion) percentiles and keys/s (keys completed divided by
- * the time from the first arrival to the last completion).
+ * (arrival to completion) percentiles (of the most recent 2^22 of them) and
+ * keys/s (keys completed divided by the time from the first arrival to the
+ * last completion).
  * pss_server_destroy cancels queued requests, waits for launched batches and
  * frees everything; no other call on the server may be in progress.
  * Every server call is thread-safe.  Error messages go to the calling

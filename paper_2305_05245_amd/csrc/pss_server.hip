@@ -177,7 +177,18 @@ struct pss_server {
   uint64_t submitted = 0, completed = 0, rejected = 0, cancelled = 0, failed = 0;
   uint64_t batches = 0, batch_requests = 0, batch_keys = 0, keys_completed = 0;
   uint64_t first_arrival = 0, last_done = 0;
+  // latencies of the most recent kLatencySamples completed requests (a ring)
+  static constexpr size_t kLatencySamples = size_t(1) << 22;
   std::vector<float> latency_ms;
+  size_t latency_next = 0;
+  void record_latency(float ms) {
+    if (latency_ms.size() < kLatencySamples) {
+      latency_ms.push_back(ms);
+    } else {
+      latency_ms[latency_next] = ms;
+      latency_next = (latency_next + 1) % kLatencySamples;
+    }
+  }
 };
 
 namespace {
@@ -314,7 +325,7 @@ void worker_loop(pss_server *sv, Worker *w) {
           ++sv->completed;
           sv->keys_completed += q.r.n;
           keys += q.r.n;
-          sv->latency_ms.push_back((float)((double)(t - q.arrival) * 1e-6));
+          sv->record_latency((float)((double)(t - q.arrival) * 1e-6));
           if (sv->first_arrival == 0 || q.arrival < sv->first_arrival) sv->first_arrival = q.arrival;
         } else {
           ++sv->failed;
@@ -436,7 +447,7 @@ pss_status pss_submit(pss_server *sv, const pss_request *req, uint64_t *ticket) 
     if (r.n == 0) {
       q.state = kDone;
       ++sv->completed;
-      sv->latency_ms.push_back((float)((double)(t > q.arrival ? t - q.arrival : 0) * 1e-6));
+      sv->record_latency((float)((double)(t > q.arrival ? t - q.arrival : 0) * 1e-6));
     } else {
       sv->queue.push_back(tk);
     }
@@ -542,6 +553,7 @@ pss_status pss_server_reset_stats(pss_server *sv) {
   sv->batches = sv->batch_requests = sv->batch_keys = sv->keys_completed = 0;
   sv->first_arrival = sv->last_done = 0;
   sv->latency_ms.clear();
+  sv->latency_next = 0;
   return PSS_OK;
 }
 

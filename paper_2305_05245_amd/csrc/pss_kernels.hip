@@ -858,39 +858,112 @@ __device__ __forceinline__ void bitonic_lane_stage(U (&key)[E], uint32_t (&tie)[
   }
 }
 
-// Slot stage of the same bitonic sort at lane distance 64 DE: slots e and
-// e + DE of one lane (every e with bit DE clear).
-template <int DE, typename U, int E>
-__device__ __forceinline__ void bitonic_slot_stage(U (&key)[E], uint32_t (&tie)[E], uint32_t lane,
-                                                   uint32_t k, uint32_t Cp) {
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    if ((e & DE) == 0 && (e | DE) < E && 64u * (e | DE) < Cp) {
-      const bool up = ((lane + 64u * e) & k) == 0;
-      cas<U, E>(key[e], tie[e], key[(e | DE) & (E - 1)], tie[(e | DE) & (E - 1)], up);
-    }
-  }
+// Byte d (0 = least significant) of the composite (key, tie): the tie's four
+// bytes below the key's.
+template <typename U>
+__device__ __forceinline__ uint32_t composite_digit(U key, uint32_t tie, int d) {
+  return d < 4 ? (tie >> (8 * d)) & 0xFFu : (uint32_t)(key >> (8 * (d - 4))) & 0xFFu;
 }
 
-// Ascending bitonic sort by (key, tie) of the Cp (a power of two, >= 64)
-// slots s = lane + 64 e of one wave: distances of 64 and more exchange slots
-// inside a lane, smaller ones exchange lanes.
+// The (key, tie) of rank k (0-based; k below the number of valid slots) among
+// the valid slots s = lane + 64 e (bit e of `valid`) of one 64-lane
+// workgroup, by radix selection: digits of 8 bits from the most significant
+// (key first, then tie), a 256-bin histogram in LDS for each, the candidates
+// narrowed to the bucket holding rank k, stopping once that bucket holds a
+// single slot.  Composites are distinct (the tie holds run and position), so
+// exactly one slot is left.  All lanes must call it.
 template <typename U, int E>
-__device__ __forceinline__ void bitonic_sort_slots(U (&key)[E], uint32_t (&tie)[E], uint32_t lane,
-                                                   uint32_t Cp) {
-  for (uint32_t k = 2; k <= Cp; k <<= 1) {
-    if constexpr (E > 16) if (k >= 128u * 16) bitonic_slot_stage<16>(key, tie, lane, k, Cp);
-    if constexpr (E > 8) if (k >= 128u * 8) bitonic_slot_stage<8>(key, tie, lane, k, Cp);
-    if constexpr (E > 4) if (k >= 128u * 4) bitonic_slot_stage<4>(key, tie, lane, k, Cp);
-    if constexpr (E > 2) if (k >= 128u * 2) bitonic_slot_stage<2>(key, tie, lane, k, Cp);
-    if constexpr (E > 1) if (k >= 128u) bitonic_slot_stage<1>(key, tie, lane, k, Cp);
-    if (k > 32) bitonic_lane_stage<32>(key, tie, lane, k, Cp);
-    if (k > 16) bitonic_lane_stage<16>(key, tie, lane, k, Cp);
-    if (k > 8) bitonic_lane_stage<8>(key, tie, lane, k, Cp);
-    if (k > 4) bitonic_lane_stage<4>(key, tie, lane, k, Cp);
-    if (k > 2) bitonic_lane_stage<2>(key, tie, lane, k, Cp);
-    bitonic_lane_stage<1>(key, tie, lane, k, Cp);
+__device__ __forceinline__ void select_rank(const U (&key)[E], const uint32_t (&tie)[E],
+                                            uint32_t valid, uint32_t k, uint32_t lane,
+                                            uint32_t *hist, U &out_key, uint32_t &out_tie) {
+  constexpr int NDIG = (int)sizeof(U) + 4;
+  uint32_t act = valid;
+  for (int d = NDIG - 1; d >= 0; --d) {
+    // a digit on which every active slot agrees narrows nothing: skip it
+    uint32_t dmin = 0xFFu, dmax = 0u;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if ((act >> e) & 1u) {
+        const uint32_t dg = composite_digit<U>(key[e], tie[e], d);
+        dmin = dg < dmin ? dg : dmin;
+        dmax = dg > dmax ? dg : dmax;
+      }
+    }
+#pragma unroll
+    for (int dd = 32; dd >= 1; dd >>= 1) {
+      const uint32_t a = __shfl_xor(dmin, dd, 64), b = __shfl_xor(dmax, dd, 64);
+      dmin = a < dmin ? a : dmin;
+      dmax = b > dmax ? b : dmax;
+    }
+    if (dmin == dmax) continue;
+    hist[lane] = 0;
+    hist[lane + 64] = 0;
+    hist[lane + 128] = 0;
+    hist[lane + 192] = 0;
+    __syncthreads();
+    // equal digits in a row of a lane's slots go in with one atomic
+    uint32_t run_d = 0u, run_c = 0u;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if ((act >> e) & 1u) {
+        const uint32_t dg = composite_digit<U>(key[e], tie[e], d);
+        if (run_c && dg == run_d) {
+          ++run_c;
+        } else {
+          if (run_c) atomicAdd(&hist[run_d], run_c);
+          run_d = dg;
+          run_c = 1u;
+        }
+      }
+    }
+    if (run_c) atomicAdd(&hist[run_d], run_c);
+    __syncthreads();
+    // lane l holds bins 4l..4l+3; the lane whose bins cover rank k picks one
+    const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1];
+    const uint32_t h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+    const uint32_t sum = h0 + h1 + h2 + h3;
+    uint32_t incl = sum;
+#pragma unroll
+    for (int dd = 1; dd < 64; dd <<= 1) {
+      const uint32_t y = __shfl_up(incl, dd, 64);
+      if ((int)lane >= dd) incl += y;
+    }
+    const uint32_t excl = incl - sum;
+    const bool mine = k >= excl && k < incl;
+    const int owner = __ffsll((unsigned long long)__ballot(mine)) - 1;
+    uint32_t v = 0, before = 0, cnt = 0;
+    if (mine) {
+      if (k < excl + h0) {
+        v = 4 * lane, before = excl, cnt = h0;
+      } else if (k < excl + h0 + h1) {
+        v = 4 * lane + 1, before = excl + h0, cnt = h1;
+      } else if (k < excl + h0 + h1 + h2) {
+        v = 4 * lane + 2, before = excl + h0 + h1, cnt = h2;
+      } else {
+        v = 4 * lane + 3, before = excl + h0 + h1 + h2, cnt = h3;
+      }
+    }
+    v = __shfl(v, owner, 64);
+    before = __shfl(before, owner, 64);
+    cnt = __shfl(cnt, owner, 64);
+    k -= before;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (composite_digit<U>(key[e], tie[e], d) != v) act &= ~(1u << e);
+    __syncthreads();  // the histogram is read before it is cleared again
+    if (cnt == 1) break;
   }
+  U kk = 0;
+  uint32_t tt = 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    if ((act >> e) & 1u) {
+      kk = key[e];
+      tt = tie[e];
+    }
+  const int owner = __ffsll((unsigned long long)__ballot(act != 0u)) - 1;
+  out_key = __shfl(kk, owner, 64);
+  out_tie = __shfl(tt, owner, 64);
 }
 
 // --------------------------------------------------------------- K2/K3 ---
@@ -911,9 +984,11 @@ __device__ __forceinline__ void bitonic_sort_slots(U (&key)[E], uint32_t (&tie)[
 // So each level loads fewer than 3F candidate samples, sorts them in LDS and
 // reads both prefixes off; at level 0, Q_lo = Q_hi = r and V_0(r) = t.
 //
-// E > 0: the candidates are sorted in registers, E slots per lane (slot s =
-// lane + 64 e, at most 64 E candidates), sTie holding each slot's run while
-// they are loaded; E = 0: they are sorted in LDS (CMAX of them).
+// E > 0: the candidates sit in registers, E slots per lane (slot s = lane +
+// 64 e, at most 64 E of them; sTie holds each slot's run while they are
+// loaded), and the two prefixes are found by selecting the candidates of rank
+// rho_lo and rho_hi (radix selection) instead of sorting; E = 0: they are
+// sorted in LDS (CMAX of them).
 template <typename U, uint32_t MAXF, int E>
 __global__ __launch_bounds__(kCorankThreads) void corank_kernel(
     const U *__restrict__ src, RunGeom g, uint32_t *__restrict__ table,
@@ -921,6 +996,7 @@ __global__ __launch_bounds__(kCorankThreads) void corank_kernel(
   constexpr uint32_t CMAX = E > 0 ? 64 * E : (MAXF <= 64 ? 256 : (MAXF <= 512 ? 2048 : 8192));
   __shared__ U sKey[E > 0 ? 1 : CMAX];
   __shared__ uint32_t sTie[CMAX];
+  __shared__ uint32_t sHist[E > 0 ? 256 : 1];
   __shared__ uint32_t sA[MAXF], sB[MAXF], sCnt[2 * MAXF], sOff[MAXF + 1];
 
   const uint32_t lane = threadIdx.x;
@@ -975,8 +1051,6 @@ __global__ __launch_bounds__(kCorankThreads) void corank_kernel(
       C = CMAX;
     }
     if constexpr (E > 0) {
-      uint32_t Cp = 64;
-      while (Cp < C) Cp <<= 1;
       for (uint32_t b = lane; b < nruns; b += 64) {
         const uint32_t o = sOff[b], c = sOff[b + 1] - o;
         for (uint32_t x = 0; x < c; ++x)
@@ -998,7 +1072,6 @@ __global__ __launch_bounds__(kCorankThreads) void corank_kernel(
           tie[e] = (b << 20) | x;
         }
       }
-      bitonic_sort_slots<U, E>(key, tie, lane, Cp);
       uint64_t rho_lo = q_lo - base, rho_hi = q_hi - base;
       if (q_lo < base || q_hi < base || rho_hi > C || rho_lo > rho_hi) {  // bracket broken
         if (lane == 0) report(kErrBracket);
@@ -1006,13 +1079,31 @@ __global__ __launch_bounds__(kCorankThreads) void corank_kernel(
         rho_hi = rho_hi > C ? C : rho_hi;
         rho_lo = rho_lo > rho_hi ? rho_hi : rho_lo;
       }
+      uint32_t valid = 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (lane + 64u * e < C) valid |= 1u << e;
+      // a candidate is among the first rho iff it is below the one of rank rho
+      U tk_lo = 0, tk_hi = 0;
+      uint32_t tt_lo = 0, tt_hi = 0;
+      if (rho_hi > 0 && rho_hi < C)
+        select_rank<U, E>(key, tie, valid, (uint32_t)rho_hi, lane, sHist, tk_hi, tt_hi);
+      if (rho_lo == rho_hi) {
+        tk_lo = tk_hi;
+        tt_lo = tt_hi;
+      } else if (rho_lo > 0 && rho_lo < C) {
+        select_rank<U, E>(key, tie, valid, (uint32_t)rho_lo, lane, sHist, tk_lo, tt_lo);
+      }
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const uint32_t s = lane + 64u * e;
-        if (s < rho_hi) {
+        if ((valid >> e) & 1u) {
           const uint32_t b = tie[e] >> 20;
-          atomicAdd(&sCnt[2 * b + 1], 1u);
-          if (s < rho_lo) atomicAdd(&sCnt[2 * b], 1u);
+          const bool hi_in = rho_hi >= C ||
+                             (rho_hi > 0 && (key[e] < tk_hi || (key[e] == tk_hi && tie[e] < tt_hi)));
+          const bool lo_in = rho_lo >= C ||
+                             (rho_lo > 0 && (key[e] < tk_lo || (key[e] == tk_lo && tie[e] < tt_lo)));
+          if (hi_in) atomicAdd(&sCnt[2 * b + 1], 1u);
+          if (lo_in) atomicAdd(&sCnt[2 * b], 1u);
         }
       }
       __syncthreads();

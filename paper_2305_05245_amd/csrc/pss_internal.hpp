@@ -43,8 +43,8 @@ constexpr uint32_t kSample = 1u << kSampleLog2;
 // Merged samples carry per-run prefix counts every kChunk entries.
 constexpr uint32_t kChunk = 64;
 // Largest fan-in for which the sampled search is used (the automatic plan's
-// passes merge at most 32 runs; the paper's single level up to 64 blocks).
-constexpr uint32_t kMaxSampledFan = 64;
+// passes merge at most 32 runs; the paper's single level up to 256 blocks).
+constexpr uint32_t kMaxSampledFan = 256;
 
 // Per-segment tables of the batched segmented sort (all device arrays, filled
 // on the device by the planning kernel).  off == nullptr: not segmented.

@@ -966,6 +966,15 @@ __device__ __forceinline__ void select_rank(const U (&key)[E], const uint32_t (&
   out_tie = __shfl(tt, owner, 64);
 }
 
+// Merged samples of one pass: the group's level-kSampleLog2 samples in
+// (key, run, position) order as run ids, plus per-run prefix counts at every
+// kChunk-th merged sample.  They give V_5(Q) for any Q without a search.
+struct SampleIndex {
+  const uint32_t *runs;  // run id of every merged sample
+  const uint32_t *prefix; // [chunk][fan]: samples of each run before the chunk
+  RunGeom gs;             // geometry of the sample array (groups align with data)
+};
+
 // --------------------------------------------------------------- K2/K3 ---
 // Exact co-rank of one target rank r over the F sorted runs of one group:
 // t_b = number of keys of run b among the r smallest keys of the group, where
@@ -989,10 +998,13 @@ __device__ __forceinline__ void select_rank(const U (&key)[E], const uint32_t (&
 // loaded), and the two prefixes are found by selecting the candidates of rank
 // rho_lo and rho_hi (radix selection) instead of sorting; E = 0: they are
 // sorted in LDS (CMAX of them).
-template <typename U, uint32_t MAXF, int E>
+//
+// SAMPLED: the search starts at level kSampleLog2 from the merged samples, as
+// in corank_wave_kernel below, with per-run counts in LDS.
+template <typename U, uint32_t MAXF, int E, bool SAMPLED = false>
 __global__ __launch_bounds__(kCorankThreads) void corank_kernel(
     const U *__restrict__ src, RunGeom g, uint32_t *__restrict__ table,
-    U *__restrict__ pivots, uint64_t *__restrict__ counts, int kt) {
+    U *__restrict__ pivots, uint64_t *__restrict__ counts, int kt, SampleIndex si) {
   constexpr uint32_t CMAX = E > 0 ? 64 * E : (MAXF <= 64 ? 256 : (MAXF <= 512 ? 2048 : 8192));
   __shared__ U sKey[E > 0 ? 1 : CMAX];
   __shared__ uint32_t sTie[CMAX];
@@ -1029,7 +1041,45 @@ __global__ __launch_bounds__(kCorankThreads) void corank_kernel(
     return num > 0 ? ((uint64_t)num >> j) : 0;
   };
 
-  for (int j = J - 1; j >= 0; --j) {
+  int jtop = J;
+  if constexpr (SAMPLED) {
+    if (!trivial && J > kSampleLog2) {
+      // V_kSampleLog2 at both bracket targets from the merged samples: the
+      // prefix counts at the chunk plus the run ids of the remaining samples
+      jtop = kSampleLog2;
+      const GroupInfo sg = group_of(si.gs, ri.grp.gi);
+      const uint64_t ns5 = sg.len, rs = si.gs.run_len;
+      const uint32_t nruns_s = ns5 ? (uint32_t)((ns5 + rs - 1) / rs) : 0u;
+      const uint64_t qs[2] = {q_lo_at(kSampleLog2),
+                              (r >> kSampleLog2) < ns5 ? (r >> kSampleLog2) : ns5};
+      const uint64_t prow0 = ri.grp.gi * (si.gs.rows_per_group - 1) * (kPart / kChunk);
+      for (int t = 0; t < 2; ++t) {
+        const uint64_t Q = qs[t];
+        for (uint32_t b = lane; b < nruns; b += 64) sCnt[b] = 0;
+        __syncthreads();
+        const uint64_t C = Q / kChunk;
+        if (Q < ns5) {
+          const uint32_t rem = (uint32_t)(Q - C * kChunk);
+          for (uint32_t i = lane; i < rem; i += 64)
+            atomicAdd(&sCnt[si.runs[sg.start + C * kChunk + i]], 1u);
+        }
+        __syncthreads();
+        for (uint32_t b = lane; b < nruns; b += 64) {
+          uint32_t v;
+          if (Q >= ns5) {
+            v = run_length(glen, R, b) >> kSampleLog2;
+          } else {
+            v = (b < nruns_s ? si.prefix[(prow0 + C) * g.fan + b] : 0u) + sCnt[b];
+          }
+          if (t == 0) sA[b] = v;
+          else sB[b] = v;
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  for (int j = jtop - 1; j >= 0; --j) {
     const uint64_t h = (uint64_t)1 << j;
     const uint64_t ns_total = (uint64_t)(nruns - 1) * (R >> j) + (lastlen >> j);
     const uint64_t q_lo = q_lo_at(j);
@@ -1239,15 +1289,6 @@ __global__ __launch_bounds__(kCorankThreads) void corank_kernel(
     }
   }
 }
-
-// Merged samples of one pass: the group's level-kSampleLog2 samples in
-// (key, run, position) order as run ids, plus per-run prefix counts at every
-// kChunk-th merged sample.  They give V_5(Q) for any Q without a search.
-struct SampleIndex {
-  const uint32_t *runs;  // run id of every merged sample
-  const uint32_t *prefix; // [chunk][fan]: samples of each run before the chunk
-  RunGeom gs;             // geometry of the sample array (groups align with data)
-};
 
 // Same search for groups of at most 64 runs, one lane per run: the prefix
 // bounds live in registers, each level's candidates are loaded one per slot
@@ -1595,7 +1636,10 @@ __global__ __launch_bounds__(NT, (VMODE == 0 && NT > kMergeThreads) ? 2 : 1) voi
   constexpr bool LABELS = MAXF <= 256;
   __shared__ uint32_t sseg[LABELS ? kPart / 4 : 1];
   __shared__ uint32_t wsum[NT / 64 + 1];
-  __shared__ uint32_t hist[VMODE == 2 ? (kPart / kChunk) * kMaxSampledFan : 1];
+  // per-run counts of a block of chunks (all chunks of a partition when
+  // the fan is at most 64)
+  constexpr uint32_t kHistWords = (kPart / kChunk) * 64;
+  __shared__ uint32_t hist[VMODE == 2 ? kHistWords : 1];
 
   const uint32_t tid = threadIdx.x;
   const PartInfo pi = part_info(g, blockIdx.x, table, part_off);
@@ -1945,20 +1989,28 @@ __global__ __launch_bounds__(NT, (VMODE == 0 && NT > kMergeThreads) ? 2 : 1) voi
       samples[sbase + i] = sk[(i << kSampleLog2) + kSample - 1];
   }
   if constexpr (VMODE == 2) {
-    // per-run prefix counts at every kChunk-th output of this partition
+    // per-run prefix counts at every kChunk-th output of this partition,
+    // counted a block of CB chunks at a time (thread b carries run b's count)
+    static_assert(MAXF <= NT, "one thread per run");
+    constexpr uint32_t CB = kHistWords / MAXF;
     const uint32_t nch = (M + kChunk - 1) / kChunk;
-    for (uint32_t i = tid; i < nch * F; i += NT) hist[i] = 0;
-    __syncthreads();
-    for (uint32_t i = tid; i < M; i += NT)
-      atomicAdd(&hist[(i / kChunk) * F + sv[i]], 1u);
-    __syncthreads();
     const uint64_t prow0 = (uint64_t)blockIdx.x * (kPart / kChunk);
-    for (uint32_t b = tid; b < F; b += NT) {
-      uint32_t run = pi.lo_row[b];
-      for (uint32_t c = 0; c < nch; ++c) {
-        prefix[(prow0 + c) * g.fan + b] = run;
-        run += hist[c * F + b];
+    uint32_t run = tid < F ? pi.lo_row[tid] : 0u;
+    for (uint32_t c0 = 0; c0 < nch; c0 += CB) {
+      const uint32_t cb = nch - c0 < CB ? nch - c0 : CB;
+      for (uint32_t i = tid; i < cb * F; i += NT) hist[i] = 0;
+      __syncthreads();
+      const uint32_t i1 = (c0 + cb) * kChunk < M ? (c0 + cb) * kChunk : M;
+      for (uint32_t i = c0 * kChunk + tid; i < i1; i += NT)
+        atomicAdd(&hist[(i / kChunk - c0) * F + sv[i]], 1u);
+      __syncthreads();
+      if (tid < F) {
+        for (uint32_t c = 0; c < cb; ++c) {
+          prefix[(prow0 + c0 + c) * g.fan + tid] = run;
+          run += hist[c * F + tid];
+        }
       }
+      __syncthreads();
     }
   }
 }
@@ -2490,8 +2542,9 @@ hipError_t launch_corank(int kt, const void *src, const RunGeom &g, uint32_t *ta
     using U = decltype(u);
     constexpr uint32_t MAXF = decltype(maxf)::value;
     constexpr int E = MAXF <= 512 ? (int)(MAXF / 16) : 0;
+    const SampleIndex none{nullptr, nullptr, g};
     hipLaunchKernelGGL((corank_kernel<U, MAXF, E>), dim3((uint32_t)rows), dim3(kCorankThreads), 0,
-                       s, (const U *)src, g, table, (U *)pivots, counts, kt);
+                       s, (const U *)src, g, table, (U *)pivots, counts, kt, none);
     return hipGetLastError();
   };
   const bool wide = key_bytes(kt) == 8;
@@ -2548,7 +2601,18 @@ hipError_t launch_corank_sampled(int kt, const void *src, const RunGeom &g, uint
   using E4 = std::integral_constant<int, 4>;
   const bool wide = key_bytes(kt) == 8;
   if (g.fan <= 32) return wide ? wave(uint64_t{}, E2{}) : wave(uint32_t{}, E2{});
-  return wide ? wave(uint64_t{}, E4{}) : wave(uint32_t{}, E4{});
+  if (g.fan <= 64) return wide ? wave(uint64_t{}, E4{}) : wave(uint32_t{}, E4{});
+  // 65-256 runs (the paper's single level only): per-run counts in LDS
+  if (g.seg.off) return hipErrorInvalidValue;
+  if (wide)
+    hipLaunchKernelGGL((corank_kernel<uint64_t, 256, 16, true>), dim3((uint32_t)rows),
+                       dim3(kCorankThreads), 0, s, (const uint64_t *)src, g, table,
+                       (uint64_t *)nullptr, (uint64_t *)nullptr, kt, si);
+  else
+    hipLaunchKernelGGL((corank_kernel<uint32_t, 256, 16, true>), dim3((uint32_t)rows),
+                       dim3(kCorankThreads), 0, s, (const uint32_t *)src, g, table,
+                       (uint32_t *)nullptr, (uint64_t *)nullptr, kt, si);
+  return hipGetLastError();
 }
 
 hipError_t launch_merge(int kt, int vmode, const void *src, const uint32_t *vsrc, void *dst,
@@ -2564,9 +2628,14 @@ hipError_t launch_merge(int kt, int vmode, const void *src, const uint32_t *vsrc
       using U = decltype(u);
       constexpr int KTI = sizeof(U) == 8 ? 2 : 0;
       MergeBufs<U> b{(const U *)src, (const U *)src, vsrc, vsrc, (U *)dst, (U *)dst, vdst, vdst};
-      hipLaunchKernelGGL((merge_kernel<KTI, 2, 64, 2 * kMergeThreads>), dim3((uint32_t)parts),
-                         dim3(2 * kMergeThreads), 0, s,
-                         b, g, table, part_offsets, 0, (U *)nullptr, prefix);
+      if (g.fan <= 64)
+        hipLaunchKernelGGL((merge_kernel<KTI, 2, 64, 2 * kMergeThreads>), dim3((uint32_t)parts),
+                           dim3(2 * kMergeThreads), 0, s,
+                           b, g, table, part_offsets, 0, (U *)nullptr, prefix);
+      else
+        hipLaunchKernelGGL((merge_kernel<KTI, 2, 256, kMergeThreads>), dim3((uint32_t)parts),
+                           dim3(kMergeThreads), 0, s,
+                           b, g, table, part_offsets, 0, (U *)nullptr, prefix);
       return hipGetLastError();
     };
     return key_bytes(kt) == 8 ? go2(uint64_t{}) : go2(uint32_t{});

@@ -312,6 +312,12 @@ void pss_graph_destroy(pss_graph *graph);
  *     request's latency; 0 = the time of submission.
  * Results are visible to any stream once pss_poll or pss_wait reports the
  * request done (the worker has synchronised its stream).
+ * A batch fails as a whole (every request in it completes with the batch's
+ * status, others are unaffected) when a launch or copy of it fails, or when
+ * the device error word (see pss_device_check) is non-zero once the batch
+ * has finished.  That word is process-wide and stays set until
+ * pss_device_check clears it, so after an invariant failure every batch that
+ * finishes fails too: no result is reported valid while it is set.
  *
  * pss_submit never blocks on the GPU and returns a ticket (> 0).  pss_poll
  * reports whether a ticket is done; pss_wait blocks until it is.  Both give
@@ -348,6 +354,8 @@ typedef struct {
   double keys_per_s;
   double latency_p50_ms, latency_p99_ms, latency_mean_ms, latency_max_ms;
   double mean_batch_requests, mean_batch_keys;
+  uint64_t budget_in_use; /* bytes of the budget held by batches now running  */
+  uint64_t queued;        /* requests waiting in the queue                      */
 } pss_stats;
 
 pss_status pss_server_create(pss_ctx *ctx, size_t hbm_budget_bytes, uint32_t max_streams,
@@ -404,6 +412,23 @@ pss_status pss_profile_read(pss_ctx *ctx, char *buf, size_t buf_len);
  * Meant for tests and debugging; it synchronises the whole device.
  */
 pss_status pss_device_check(pss_ctx *ctx, uint32_t *code);
+
+/*
+ * Fault injection, for tests of failure handling (process-wide, thread-safe).
+ * Arms one operation of the given kind to fail: the library lets `after`
+ * more operations of that kind through, then the next one is not performed
+ * and its call returns the error a refusing runtime would cause, with a
+ * message naming the injection; the arming is then used up.
+ *   PSS_INJECT_LAUNCH: queued device work (a kernel launch, an asynchronous
+ *     copy or fill) made by any call, the server's workers included; the call
+ *     returns PSS_ERR_HIP and work it queued before that point stays queued.
+ *   PSS_INJECT_ALLOC: a device or pinned host allocation (the serving
+ *     loop's buffers at pss_server_create); the call returns PSS_ERR_BUDGET.
+ *   PSS_INJECT_NONE: disarm both kinds (after is ignored).
+ * after < 0 disarms the kind.  Not for production use.
+ */
+typedef enum { PSS_INJECT_NONE = 0, PSS_INJECT_LAUNCH = 1, PSS_INJECT_ALLOC = 2 } pss_inject_t;
+pss_status pss_debug_inject(pss_inject_t what, int64_t after);
 
 #ifdef __cplusplus
 }

@@ -47,10 +47,16 @@ def _context(device: int) -> _lib.Context:
 
 
 class Workspace:
-    """Grow-only device scratch buffer, one per device (caller-owned memory
-    handed to the library as `ws`)."""
+    """Grow-only device scratch buffer (caller-owned memory handed to the
+    library as `ws`), one per (device, stream).
 
-    _per_device: dict[int, "Workspace"] = {}
+    Work queued on one stream runs in order, so a buffer that only that
+    stream uses is never read by one sort while another writes it, and when
+    it grows, the caching allocator hands the old block out again only to
+    work ordered after the sorts already queued on the same stream."""
+
+    _lock = threading.Lock()
+    _per_stream: dict[tuple[int, int], "Workspace"] = {}
 
     def __init__(self, device: int):
         self.device = device
@@ -58,12 +64,16 @@ class Workspace:
 
     @classmethod
     def get(cls, device: int, nbytes: int) -> torch.Tensor:
-        ws = cls._per_device.get(device)
-        if ws is None:
-            ws = cls._per_device[device] = cls(device)
-        if ws.buf.numel() < nbytes:
-            ws.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{device}")
-        return ws.buf
+        """The current stream's buffer on `device`, grown to nbytes."""
+        key = (device, _stream_handle(device))
+        with cls._lock:
+            ws = cls._per_stream.get(key)
+            if ws is None:
+                ws = cls._per_stream[key] = cls(device)
+            if ws.buf.numel() < nbytes:
+                ws.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8,
+                                     device=f"cuda:{device}")
+            return ws.buf
 
 
 def key_type_of(t: torch.Tensor, key_type: str | int | None = None) -> int:

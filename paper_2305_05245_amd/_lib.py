@@ -20,6 +20,8 @@ KEY_NAMES = {"u32": U32, "i32": I32, "u64": U64, "i64": I64, "f32": F32, "f64": 
 KEY_BYTES = {U32: 4, I32: 4, U64: 8, I64: 8, F32: 4, F64: 8}
 # pss_val_t
 VAL_NONE, VAL_U32 = 0, 1
+# pss_inject_t
+INJECT_NONE, INJECT_LAUNCH, INJECT_ALLOC = 0, 1, 2
 # pss_status
 (OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_OOM, ERR_HIP, ERR_WORKSPACE, ERR_BUDGET, ERR_BUSY,
  ERR_CANCELLED) = range(9)
@@ -42,7 +44,8 @@ class Stats(ctypes.Structure):
                                                "failed", "batches", "keys_completed")] + \
                [(f, ctypes.c_double) for f in ("keys_per_s", "latency_p50_ms", "latency_p99_ms",
                                                "latency_mean_ms", "latency_max_ms",
-                                               "mean_batch_requests", "mean_batch_keys")]
+                                               "mean_batch_requests", "mean_batch_keys")] + \
+               [(f, ctypes.c_uint64) for f in ("budget_in_use", "queued")]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -88,6 +91,7 @@ SIGNATURES = {
                              _vp]),
     "pss_psrs_splitters": (_int, [_vp, _int, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp,
                                   _sz, _vp]),
+    "pss_debug_inject": (_int, [_int, _c.c_int64]),
 }
 
 _lock = threading.Lock()
@@ -116,6 +120,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                 fn.argtypes = args
             _lib = lib
     return _lib
+
+
+def debug_inject(what: int, after: int = 0) -> None:
+    """pss_debug_inject: arm the (after+1)-th next operation of a kind to fail
+    (INJECT_LAUNCH, INJECT_ALLOC); INJECT_NONE or after < 0 disarms."""
+    check(load().pss_debug_inject(what, after))
 
 
 def status_string(status: int) -> str:
@@ -216,7 +226,12 @@ class Graph:
 
 
 class Context:
-    """One pss_ctx bound to a HIP device."""
+    """One pss_ctx bound to a HIP device.
+
+    A pss_ctx may be used by one thread at a time (include/pss.h), while
+    Python code may share a Context between threads: every call into the
+    library, together with the read of the context's last error message,
+    holds the context's lock."""
 
     def __init__(self, device: int = 0):
         self.lib = load()
@@ -224,10 +239,16 @@ class Context:
         check(self.lib.pss_create(device, ctypes.byref(h)))
         self.handle = h
         self.device = device
+        self._mu = threading.RLock()
+
+    def _call(self, name: str, *args) -> None:
+        with self._mu:
+            check(getattr(self.lib, name)(self.handle, *args), self.handle)
 
     def close(self):
         if self.handle:
-            self.lib.pss_destroy(self.handle)
+            with self._mu:
+                self.lib.pss_destroy(self.handle)
             self.handle = ctypes.c_void_p()
 
     def __del__(self):
@@ -238,73 +259,71 @@ class Context:
 
     def sort(self, key: int, val: int, keys_in: int, keys_out: int, vals_in: int, vals_out: int,
              n: int, n_blocks: int, n_parts: int, ws: int, ws_bytes: int, stream: int) -> None:
-        check(self.lib.pss_sort(self.handle, key, val, keys_in or None, keys_out or None,
-                                vals_in or None, vals_out or None, n, n_blocks, n_parts,
-                                ws or None, ws_bytes, stream or None), self.handle)
+        self._call("pss_sort", key, val, keys_in or None, keys_out or None,
+                   vals_in or None, vals_out or None, n, n_blocks, n_parts,
+                   ws or None, ws_bytes, stream or None)
 
     def profile(self, on: bool) -> None:
-        check(self.lib.pss_profile_enable(self.handle, 1 if on else 0), self.handle)
+        self._call("pss_profile_enable", 1 if on else 0)
 
     def profile_read(self) -> dict:
         buf = ctypes.create_string_buffer(1 << 16)
-        check(self.lib.pss_profile_read(self.handle, buf, len(buf)), self.handle)
+        self._call("pss_profile_read", buf, len(buf))
         return json.loads(buf.value.decode())
 
     def segmented_sort(self, key: int, val: int, keys_in: int, keys_out: int, vals_in: int,
                        vals_out: int, n: int, seg_offsets: int, n_segs: int,
                        tuning: Tuning | None, ws: int, ws_bytes: int, stream: int) -> None:
-        check(self.lib.pss_segmented_sort(self.handle, key, val, keys_in or None, keys_out or None,
-                                          vals_in or None, vals_out or None, n, seg_offsets or None,
-                                          n_segs, ctypes.byref(tuning) if tuning else None,
-                                          ws or None, ws_bytes, stream or None), self.handle)
+        self._call("pss_segmented_sort", key, val, keys_in or None, keys_out or None,
+                   vals_in or None, vals_out or None, n, seg_offsets or None,
+                   n_segs, ctypes.byref(tuning) if tuning else None,
+                   ws or None, ws_bytes, stream or None)
 
     def segmented_graph(self, key: int, val: int, keys_in: int, keys_out: int, vals_in: int,
                         vals_out: int, n: int, seg_offsets: int, n_segs: int,
                         tuning: Tuning | None, ws: int, ws_bytes: int) -> "Graph":
         h = ctypes.c_void_p()
-        check(self.lib.pss_segmented_graph_create(
-            self.handle, key, val, keys_in or None, keys_out or None, vals_in or None,
-            vals_out or None, n, seg_offsets or None, n_segs,
-            ctypes.byref(tuning) if tuning else None, ws or None, ws_bytes, ctypes.byref(h)),
-            self.handle)
+        self._call("pss_segmented_graph_create", key, val, keys_in or None, keys_out or None,
+                   vals_in or None, vals_out or None, n, seg_offsets or None, n_segs,
+                   ctypes.byref(tuning) if tuning else None, ws or None, ws_bytes,
+                   ctypes.byref(h))
         return Graph(self.lib, h)
 
     def device_check(self) -> int:
         """Synchronise the device and return (and clear) the error word."""
         code = ctypes.c_uint32()
-        check(self.lib.pss_device_check(self.handle, ctypes.byref(code)), self.handle)
+        self._call("pss_device_check", ctypes.byref(code))
         return int(code.value)
 
     def set_merge_method(self, method: int) -> None:
-        check(self.lib.pss_set_merge_method(self.handle, method), self.handle)
+        self._call("pss_set_merge_method", method)
 
     def sort_records(self, key: int, records_in: int, records_out: int, n: int,
                      record_bytes: int, key_offset: int, ws: int, ws_bytes: int,
                      stream: int) -> None:
-        check(self.lib.pss_sort_records(self.handle, key, records_in or None, records_out or None,
-                                        n, record_bytes, key_offset, ws or None, ws_bytes,
-                                        stream or None), self.handle)
+        self._call("pss_sort_records", key, records_in or None, records_out or None,
+                   n, record_bytes, key_offset, ws or None, ws_bytes,
+                   stream or None)
 
     def psrs_sort(self, key: int, val: int, keys_in: int, keys_out: int, vals_in: int,
                   vals_out: int, n: int, n_blocks: int, n_parts: int, part_sizes: int, ws: int,
                   ws_bytes: int, stream: int) -> None:
-        check(self.lib.pss_psrs_sort(self.handle, key, val, keys_in or None, keys_out or None,
-                                     vals_in or None, vals_out or None, n, n_blocks, n_parts,
-                                     part_sizes or None, ws or None, ws_bytes, stream or None),
-              self.handle)
+        self._call("pss_psrs_sort", key, val, keys_in or None, keys_out or None,
+                   vals_in or None, vals_out or None, n, n_blocks, n_parts,
+                   part_sizes or None, ws or None, ws_bytes, stream or None)
 
     def psrs_splitters(self, key: int, keys_in: int, n: int, n_blocks: int, n_parts: int,
                        sorted_blocks: int, samples: int, pivots: int, split: int, offsets: int,
                        ws: int, ws_bytes: int, stream: int) -> None:
-        check(self.lib.pss_psrs_splitters(self.handle, key, keys_in or None, n, n_blocks, n_parts,
-                                          sorted_blocks or None, samples or None, pivots or None,
-                                          split or None, offsets or None, ws or None, ws_bytes,
-                                          stream or None), self.handle)
+        self._call("pss_psrs_splitters", key, keys_in or None, n, n_blocks, n_parts,
+                   sorted_blocks or None, samples or None, pivots or None,
+                   split or None, offsets or None, ws or None, ws_bytes,
+                   stream or None)
 
     def splitters(self, key: int, keys_in: int, n: int, n_blocks: int, n_parts: int,
                   sorted_blocks: int, pivots: int, counts: int, split: int, offsets: int,
                   ws: int, ws_bytes: int, stream: int) -> None:
-        check(self.lib.pss_splitters(self.handle, key, keys_in or None, n, n_blocks, n_parts,
-                                     sorted_blocks or None, pivots or None, counts or None,
-                                     split or None, offsets or None, ws or None, ws_bytes,
-                                     stream or None), self.handle)
+        self._call("pss_splitters", key, keys_in or None, n, n_blocks, n_parts,
+                   sorted_blocks or None, pivots or None, counts or None,
+                   split or None, offsets or None, ws or None, ws_bytes,
+                   stream or None)

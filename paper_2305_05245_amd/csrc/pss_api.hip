@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -246,6 +247,15 @@ pss_status validate(const pss_ctx *ctx, pss_key_t key, pss_val_t val, const void
     if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
   } while (0)
 
+// Queued device work (kernel launches, async copies and fills): as PSS_TRY,
+// and the operation pss_debug_inject armed fails instead of being queued.
+#define PSS_LAUNCH(expr, what)                                                         \
+  do {                                                                                 \
+    if (pss::inject_fault(pss::kInjectLaunch))                                         \
+      return fail(ctx, PSS_ERR_HIP, std::string(what) + ": injected fault (pss_debug_inject)"); \
+    PSS_TRY(expr, what);                                                               \
+  } while (0)
+
 // Optional per-launch timing: when profiling is on, every kernel launch is
 // bracketed by two events recorded on the launch stream.
 hipEvent_t take_event(pss_ctx *ctx) {
@@ -305,7 +315,7 @@ pss_status run_segment_sort(pss_ctx *ctx, const Plan &p, int kt, const void *key
   uint32_t *prefix = (uint32_t *)(w + p.off_prefix);
   {
     LaunchTimer t(ctx, "tile_sort", sweep, s);
-    PSS_TRY(pss::launch_tile_sort(kt, p.kv, keys_in, vals_in, kbuf[0], vbuf[0], p.n, p.seg_len,
+    PSS_LAUNCH(pss::launch_tile_sort(kt, p.kv, keys_in, vals_in, kbuf[0], vbuf[0], p.n, p.seg_len,
                                   final_last && P == 0, samples, s),
             "tile sort launch");
   }
@@ -315,23 +325,23 @@ pss_status run_segment_sort(pss_ctx *ctx, const Plan &p, int kt, const void *key
     const uint64_t sbytes = gs.n * (uint64_t)p.kb;
     {
       LaunchTimer t(ctx, "sample_split_search", gs.total_rows() * gs.fan * 4, s);
-      PSS_TRY(pss::launch_corank(kt, samples, gs, stable, nullptr, nullptr, s),
+      PSS_LAUNCH(pss::launch_corank(kt, samples, gs, stable, nullptr, nullptr, s),
               "sample split search launch");
     }
     {
       LaunchTimer t(ctx, "sample_merge", 2 * sbytes + gs.n * 4, s);
-      PSS_TRY(pss::launch_merge(kt, 2, samples, nullptr, skeys, sruns, gs, stable, nullptr, 0,
+      PSS_LAUNCH(pss::launch_merge(kt, 2, samples, nullptr, skeys, sruns, gs, stable, nullptr, 0,
                                 nullptr, prefix, s),
               "sample merge launch");
     }
     {
       LaunchTimer t(ctx, "split_search", g.total_rows() * g.fan * 4, s);
-      PSS_TRY(pss::launch_corank_sampled(kt, kbuf[q - 1], g, table, sruns, prefix, s),
+      PSS_LAUNCH(pss::launch_corank_sampled(kt, kbuf[q - 1], g, table, sruns, prefix, s),
               "split search launch");
     }
     {
       LaunchTimer t(ctx, "merge", sweep, s);
-      PSS_TRY(pss::launch_merge(kt, p.kv ? 1 : 0, kbuf[q - 1], vbuf[q - 1], kbuf[q], vbuf[q], g,
+      PSS_LAUNCH(pss::launch_merge(kt, p.kv ? 1 : 0, kbuf[q - 1], vbuf[q - 1], kbuf[q], vbuf[q], g,
                                 table, nullptr, final_last && q == P,
                                 q < P ? samples : last_samples, nullptr, s),
               "merge launch");
@@ -360,7 +370,7 @@ pss_status paper_partition_search(pss_ctx *ctx, const Plan &p, int kt, const voi
                                   hipStream_t s) {
   if (!p.top_sampled) {
     LaunchTimer t(ctx, "partition_search", top.total_rows() * top.fan * 4, s);
-    PSS_TRY(pss::launch_corank(kt, blocks, top, table, nullptr, nullptr, s), "splitter launch");
+    PSS_LAUNCH(pss::launch_corank(kt, blocks, top, table, nullptr, nullptr, s), "splitter launch");
     return PSS_OK;
   }
   const pss::RunGeom &gs = p.top_gs;
@@ -371,18 +381,18 @@ pss_status paper_partition_search(pss_ctx *ctx, const Plan &p, int kt, const voi
   uint32_t *prefix = (uint32_t *)(w + p.off_prefix);
   {
     LaunchTimer t(ctx, "partition_sample_search", gs.total_rows() * gs.fan * 4, s);
-    PSS_TRY(pss::launch_corank(kt, samples, gs, stable, nullptr, nullptr, s),
+    PSS_LAUNCH(pss::launch_corank(kt, samples, gs, stable, nullptr, nullptr, s),
             "sample split search launch");
   }
   {
     LaunchTimer t(ctx, "partition_sample_merge", 2 * gs.n * (uint64_t)p.kb + gs.n * 4, s);
-    PSS_TRY(pss::launch_merge(kt, 2, samples, nullptr, skeys, sruns, gs, stable, nullptr, 0,
+    PSS_LAUNCH(pss::launch_merge(kt, 2, samples, nullptr, skeys, sruns, gs, stable, nullptr, 0,
                               nullptr, prefix, s),
             "sample merge launch");
   }
   {
     LaunchTimer t(ctx, "partition_search", top.total_rows() * top.fan * 4, s);
-    PSS_TRY(pss::launch_corank_sampled(kt, blocks, top, table, sruns, prefix, s, nullptr, &gs),
+    PSS_LAUNCH(pss::launch_corank_sampled(kt, blocks, top, table, sruns, prefix, s, nullptr, &gs),
             "splitter launch");
   }
   return PSS_OK;
@@ -501,7 +511,7 @@ pss_status run_psrs(pss_ctx *ctx, const PsrsPlan &pp, int kt, const void *keys_i
   if (pp.ns) {
     {
       LaunchTimer t(ctx, "psrs_samples", pp.ns * kbytes * 2, s);
-      PSS_TRY(pss::launch_psrs_samples(kt, blocks, pp.top, samples, s), "sample launch");
+      PSS_LAUNCH(pss::launch_psrs_samples(kt, blocks, pp.top, samples, s), "sample launch");
     }
     {
       // one timing record for the whole sample sort
@@ -514,24 +524,24 @@ pss_status run_psrs(pss_ctx *ctx, const PsrsPlan &pp, int kt, const void *keys_i
       if (st != PSS_OK) return st;
     }
     if (o.samples)
-      PSS_TRY(pss::launch_unmap_copy(kt, ssorted, o.samples, pp.ns, s), "sample copy");
+      PSS_LAUNCH(pss::launch_unmap_copy(kt, ssorted, o.samples, pp.ns, s), "sample copy");
   }
   {
     LaunchTimer t(ctx, "psrs_partition", (uint64_t)p.top.fan * (p.top.n_parts + 1) * 8, s);
-    PSS_TRY(pss::launch_psrs_partition(kt, blocks, pp.top, ssorted, pp.ns, bounds, o.pivots,
+    PSS_LAUNCH(pss::launch_psrs_partition(kt, blocks, pp.top, ssorted, pp.ns, bounds, o.pivots,
                                        o.split, s),
             "partition launch");
   }
   {
     LaunchTimer t(ctx, "psrs_chunks", (uint64_t)p.top.n_parts * 24, s);
-    PSS_TRY(pss::launch_psrs_chunks(pp.top, bounds, o.sizes, chunks, cprefix, s), "chunk launch");
+    PSS_LAUNCH(pss::launch_psrs_chunks(pp.top, bounds, o.sizes, chunks, cprefix, s), "chunk launch");
   }
   if (o.offsets)
-    PSS_TRY(hipMemcpyAsync(o.offsets, bounds, ((size_t)p.top.n_parts + 1) * 8,
+    PSS_LAUNCH(hipMemcpyAsync(o.offsets, bounds, ((size_t)p.top.n_parts + 1) * 8,
                            hipMemcpyDeviceToDevice, s),
             "offset copy");
   if (o.sorted_blocks)
-    PSS_TRY(pss::launch_unmap_copy(kt, blocks, o.sorted_blocks, p.n, s), "block copy");
+    PSS_LAUNCH(pss::launch_unmap_copy(kt, blocks, o.sorted_blocks, p.n, s), "block copy");
   if (!merge) return PSS_OK;
   pss::RunGeom top = pp.top;
   top.bounds = bounds;
@@ -542,11 +552,11 @@ pss_status run_psrs(pss_ctx *ctx, const PsrsPlan &pp, int kt, const void *keys_i
   {
     LaunchTimer t(ctx, "partition_merge", 2 * p.n * ((uint64_t)p.kb + (p.kv ? 4 : 0)), s);
     if (ctx->merge_method == PSS_MERGE_SORT)
-      PSS_TRY(pss::launch_sort_merge(kt, p.kv, blocks, vbuf[P], keys_out, vals_out, top, table,
+      PSS_LAUNCH(pss::launch_sort_merge(kt, p.kv, blocks, vbuf[P], keys_out, vals_out, top, table,
                                      nullptr, 1, s),
               "merge launch");
     else
-      PSS_TRY(pss::launch_merge(kt, p.kv ? 1 : 0, blocks, vbuf[P], keys_out, vals_out, top, table,
+      PSS_LAUNCH(pss::launch_merge(kt, p.kv ? 1 : 0, blocks, vbuf[P], keys_out, vals_out, top, table,
                                 nullptr, 1, nullptr, nullptr, s),
               "merge launch");
   }
@@ -610,11 +620,55 @@ pss_status record_plan(const pss_ctx *ctx, pss_key_t key, uint64_t n, RecordPlan
 }  // namespace
 
 namespace pss {
+RunGeom sample_geom(const RunGeom &g) {
+  RunGeom s = g;
+  const uint64_t nseg = (g.n + g.seg_len - 1) / g.seg_len;
+  const uint64_t last = g.n - (nseg - 1) * g.seg_len;
+  s.seg_len = g.seg_len >> kSampleLog2;
+  s.n = (nseg - 1) * s.seg_len + (last >> kSampleLog2);
+  s.run_len = g.run_len >> kSampleLog2;
+  s.group_len = g.group_len >> kSampleLog2;
+  s.part_len = kPart;
+  s.rows_per_group = (uint32_t)((s.group_len + kPart - 1) / kPart) + 1;
+  return s;
+}
+
 void set_thread_error(const char *msg) { g_thread_error = msg; }
 int ctx_device(const pss_ctx *ctx) { return ctx->device; }
 }  // namespace pss
 
+namespace pss {
+
+namespace {
+// Operations of each kind still allowed before the armed one fails; -1 = not
+// armed.  Index: kInjectLaunch, kInjectAlloc.
+std::atomic<int64_t> g_inject[3] = {{-1}, {-1}, {-1}};
+}  // namespace
+
+bool inject_fault(int kind) {
+  std::atomic<int64_t> &c = g_inject[kind];
+  int64_t v = c.load(std::memory_order_relaxed);
+  while (v >= 0) {
+    if (c.compare_exchange_weak(v, v - 1, std::memory_order_acq_rel)) return v == 0;
+  }
+  return false;
+}
+
+}  // namespace pss
+
 extern "C" {
+
+pss_status pss_debug_inject(pss_inject_t what, int64_t after) {
+  if (!pss::valid_enum(what, 2)) return fail(nullptr, PSS_ERR_INVALID, "unknown fault kind");
+  if (what == PSS_INJECT_NONE) {
+    pss::g_inject[pss::kInjectLaunch].store(-1);
+    pss::g_inject[pss::kInjectAlloc].store(-1);
+    return PSS_OK;
+  }
+  pss::g_inject[what == PSS_INJECT_LAUNCH ? pss::kInjectLaunch : pss::kInjectAlloc].store(
+      after < 0 ? -1 : after);
+  return PSS_OK;
+}
 
 pss_status pss_create(int device, pss_ctx **out) {
   if (!out) return fail(nullptr, PSS_ERR_INVALID, "null output handle");
@@ -644,8 +698,7 @@ void pss_destroy(pss_ctx *ctx) {
 
 pss_status pss_set_merge_method(pss_ctx *ctx, pss_merge_method method) {
   if (!ctx) return fail(nullptr, PSS_ERR_INVALID, "null context");
-  if (method != PSS_MERGE_PAIRWISE && method != PSS_MERGE_SORT)
-    return fail(ctx, PSS_ERR_INVALID, "unknown merge method");
+  if (!pss::valid_enum(method, 1)) return fail(ctx, PSS_ERR_INVALID, "unknown merge method");
   ctx->merge_method = method;
   return PSS_OK;
 }
@@ -718,6 +771,8 @@ const char *pss_last_error(const pss_ctx *ctx) {
 pss_status pss_validate(pss_key_t key, pss_val_t val, const void *keys_in, const void *keys_out,
                         const void *vals_in, const void *vals_out, uint64_t n, uint32_t n_blocks,
                         uint32_t n_parts, size_t ws_bytes) {
+  if (!pss::valid_enum(key, 5) || !pss::valid_enum(val, 1))
+    return fail(nullptr, PSS_ERR_INVALID, "unknown key or value type");
   Plan p;
   return validate(nullptr, key, val, keys_in, keys_out, vals_in, vals_out, n, n_blocks, n_parts,
                   ws_bytes, &p);
@@ -725,6 +780,8 @@ pss_status pss_validate(pss_key_t key, pss_val_t val, const void *keys_in, const
 
 pss_status pss_workspace_bytes(const pss_ctx *ctx, pss_key_t key, pss_val_t val, uint64_t n,
                                uint32_t n_blocks, uint32_t n_parts, size_t *bytes) {
+  if (!pss::valid_enum(key, 5) || !pss::valid_enum(val, 1))
+    return fail(ctx, PSS_ERR_INVALID, "unknown key or value type");
   if (!bytes) return fail(ctx, PSS_ERR_INVALID, "null output pointer");
   Plan p;
   // enum, mode and limit checks only (no arrays exist yet)
@@ -741,6 +798,8 @@ pss_status pss_workspace_bytes(const pss_ctx *ctx, pss_key_t key, pss_val_t val,
 
 pss_status pss_plan_describe(pss_key_t key, pss_val_t val, uint64_t n, uint32_t n_blocks,
                              uint32_t n_parts, char *buf, size_t buf_len) {
+  if (!pss::valid_enum(key, 5) || !pss::valid_enum(val, 1))
+    return fail(nullptr, PSS_ERR_INVALID, "unknown key or value type");
   if (!buf || buf_len == 0) return fail(nullptr, PSS_ERR_INVALID, "null buffer");
   size_t ws = 0;
   const pss_status s = pss_workspace_bytes(nullptr, key, val, n, n_blocks, n_parts, &ws);
@@ -771,6 +830,8 @@ pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys
                     void *keys_out, const uint32_t *vals_in, uint32_t *vals_out, uint64_t n,
                     uint32_t n_blocks, uint32_t n_parts, void *ws, size_t ws_bytes,
                     void *stream) {
+  if (!pss::valid_enum(key, 5) || !pss::valid_enum(val, 1))
+    return fail(ctx, PSS_ERR_INVALID, "unknown key or value type");
   Plan p;
   pss_status st = validate(ctx, key, val, keys_in, keys_out, vals_in, vals_out, n, n_blocks,
                            n_parts, ws_bytes, &p);
@@ -806,16 +867,16 @@ pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys
     if (st != PSS_OK) return st;
     {
       LaunchTimer t(ctx, "offset_scan", (uint64_t)p.top.n_parts * 16, s);
-      PSS_TRY(pss::launch_partition_offsets(p.top, table, sizes, offsets, s), "offset scan launch");
+      PSS_LAUNCH(pss::launch_partition_offsets(p.top, table, sizes, offsets, s), "offset scan launch");
     }
     {
       LaunchTimer t(ctx, "partition_merge", sweep, s);
       if (ctx->merge_method == PSS_MERGE_SORT)
-        PSS_TRY(pss::launch_sort_merge(kt, p.kv, kb[P], vb[P], keys_out, vals_out, p.top, table,
+        PSS_LAUNCH(pss::launch_sort_merge(kt, p.kv, kb[P], vb[P], keys_out, vals_out, p.top, table,
                                        offsets, 1, s),
                 "merge launch");
       else
-        PSS_TRY(pss::launch_merge(kt, p.kv ? 1 : 0, kb[P], vb[P], keys_out, vals_out, p.top,
+        PSS_LAUNCH(pss::launch_merge(kt, p.kv ? 1 : 0, kb[P], vb[P], keys_out, vals_out, p.top,
                                   table, offsets, 1, nullptr, nullptr, s),
                 "merge launch");
     }
@@ -935,6 +996,8 @@ pss::SegPlanPtrs seg_plan_ptrs(char *w, const SegPlan &sp, uint32_t n_segs) {
 pss_status pss_segmented_workspace_bytes(const pss_ctx *ctx, pss_key_t key, pss_val_t val,
                                          uint64_t n, uint32_t n_segs, const pss_tuning *tuning,
                                          size_t *bytes) {
+  if (!pss::valid_enum(key, 5) || !pss::valid_enum(val, 1))
+    return fail(ctx, PSS_ERR_INVALID, "unknown key or value type");
   if (!bytes) return fail(ctx, PSS_ERR_INVALID, "null output pointer");
   SegPlan sp;
   const pss_status st = make_seg_plan(ctx, key, val, n, n_segs, tuning, &sp);
@@ -947,6 +1010,8 @@ pss_status pss_segmented_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const 
                               void *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
                               uint64_t n, const uint64_t *seg_offsets, uint32_t n_segs,
                               const pss_tuning *tuning, void *ws, size_t ws_bytes, void *stream) {
+  if (!pss::valid_enum(key, 5) || !pss::valid_enum(val, 1))
+    return fail(ctx, PSS_ERR_INVALID, "unknown key or value type");
   SegPlan sp;
   pss_status st = make_seg_plan(ctx, key, val, n, n_segs, tuning, &sp);
   if (st != PSS_OK) return st;
@@ -987,12 +1052,12 @@ pss_status pss_segmented_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const 
   const uint64_t sweep = 2 * n * (kbytes + (kv ? 4 : 0));
   {
     LaunchTimer t(ctx, "segment_plan", (uint64_t)n_segs * 16, s);
-    PSS_TRY(pss::launch_seg_plan(seg_offsets, n_segs, n, pp, sp.small0, sp.small1, sp.max_passes, s),
+    PSS_LAUNCH(pss::launch_seg_plan(seg_offsets, n_segs, n, pp, sp.small0, sp.small1, sp.max_passes, s),
             "segment plan launch");
   }
   {
     LaunchTimer t(ctx, "tile_sort", sweep, s);
-    PSS_TRY(pss::launch_seg_tile_sorts(kt, kv, keys_in, vals_in, keys_out, kws, vals_out, vws,
+    PSS_LAUNCH(pss::launch_seg_tile_sorts(kt, kv, keys_in, vals_in, keys_out, kws, vals_out, vws,
                                        samples, seg_offsets, pp, n_segs, n, s),
             "tile sort launch");
   }
@@ -1004,24 +1069,24 @@ pss_status pss_segmented_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const 
                             pp.sparts[q - 1], n_segs, q, 1};
     {
       LaunchTimer t(ctx, "sample_split_search", gs.row_bound * gs.fan * 4, s);
-      PSS_TRY(pss::launch_corank(kt, samples, gs, stable, nullptr, nullptr, s),
+      PSS_LAUNCH(pss::launch_corank(kt, samples, gs, stable, nullptr, nullptr, s),
               "sample split search launch");
     }
     {
       LaunchTimer t(ctx, "sample_merge", 2 * sp.ns * kbytes, s);
-      PSS_TRY(pss::launch_merge(kt, 2, samples, nullptr, skeys, sruns, gs, stable, nullptr, 0, nullptr,
+      PSS_LAUNCH(pss::launch_merge(kt, 2, samples, nullptr, skeys, sruns, gs, stable, nullptr, 0, nullptr,
                                 prefix, s),
               "sample merge launch");
     }
     {
       LaunchTimer t(ctx, "split_search", g.row_bound * g.fan * 4, s);
-      PSS_TRY(pss::launch_corank_sampled(kt, keys_out, g, table, sruns, prefix, s, kws, &gs),
+      PSS_LAUNCH(pss::launch_corank_sampled(kt, keys_out, g, table, sruns, prefix, s, kws, &gs),
               "split search launch");
     }
     {
       LaunchTimer t(ctx, "merge", sweep, s);
       const pss::MergeAlt alt{kws, vws, kws, vws};
-      PSS_TRY(pss::launch_merge(kt, kv ? 1 : 0, keys_out, vals_out, keys_out, vals_out, g, table,
+      PSS_LAUNCH(pss::launch_merge(kt, kv ? 1 : 0, keys_out, vals_out, keys_out, vals_out, g, table,
                                 nullptr, 0, samples, nullptr, s, &alt),
               "merge launch");
     }
@@ -1041,6 +1106,8 @@ pss_status pss_segmented_graph_create(pss_ctx *ctx, pss_key_t key, pss_val_t val
                                       const uint64_t *seg_offsets, uint32_t n_segs,
                                       const pss_tuning *tuning, void *ws, size_t ws_bytes,
                                       pss_graph **out) {
+  if (!pss::valid_enum(key, 5) || !pss::valid_enum(val, 1))
+    return fail(ctx, PSS_ERR_INVALID, "unknown key or value type");
   if (!out) return fail(ctx, PSS_ERR_INVALID, "null output handle");
   *out = nullptr;
   if (!ctx) return fail(nullptr, PSS_ERR_INVALID, "null context");
@@ -1117,6 +1184,8 @@ pss_status pss_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, uint6
                          uint32_t n_blocks, uint32_t n_parts, void *sorted_blocks, void *pivots,
                          uint64_t *counts, uint64_t *split, uint64_t *offsets, void *ws,
                          size_t ws_bytes, void *stream) {
+  if (!pss::valid_enum(key, 5))
+    return fail(ctx, PSS_ERR_INVALID, "unknown key or value type");
   if (n_blocks == 0 || n_parts == 0)
     return fail(ctx, PSS_ERR_INVALID, "pss_splitters needs n_blocks > 0 and n_parts > 0");
   Plan p;
@@ -1135,11 +1204,11 @@ pss_status pss_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, uint6
   const int kbytes = pss::key_bytes(kt);
   if (n == 0) {
     if (counts && n_parts > 1)
-      PSS_TRY(hipMemsetAsync(counts, 0, (n_parts - 1) * sizeof(uint64_t), s), "memset");
+      PSS_LAUNCH(hipMemsetAsync(counts, 0, (n_parts - 1) * sizeof(uint64_t), s), "memset");
     if (pivots && n_parts > 1)
-      PSS_TRY(hipMemsetAsync(pivots, 0, (size_t)(n_parts - 1) * kbytes, s), "memset");
-    if (split) PSS_TRY(hipMemsetAsync(split, 0, (size_t)n_blocks * (n_parts + 1) * 8, s), "memset");
-    if (offsets) PSS_TRY(hipMemsetAsync(offsets, 0, ((size_t)n_parts + 1) * 8, s), "memset");
+      PSS_LAUNCH(hipMemsetAsync(pivots, 0, (size_t)(n_parts - 1) * kbytes, s), "memset");
+    if (split) PSS_LAUNCH(hipMemsetAsync(split, 0, (size_t)n_blocks * (n_parts + 1) * 8, s), "memset");
+    if (offsets) PSS_LAUNCH(hipMemsetAsync(offsets, 0, ((size_t)n_parts + 1) * 8, s), "memset");
     return PSS_OK;
   }
   char *w = (char *)ws;
@@ -1158,19 +1227,21 @@ pss_status pss_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, uint6
   // pivots and counts are written by the splitter search (both or neither)
   void *piv_dev = n_parts > 1 ? pivots : nullptr;
   uint64_t *cnt_dev = n_parts > 1 ? counts : nullptr;
-  PSS_TRY(pss::launch_corank(kt, kb[P], p.top, table, piv_dev, cnt_dev, s), "splitter launch");
-  PSS_TRY(pss::launch_partition_offsets(p.top, table, sizes, offs, s), "offset scan launch");
+  PSS_LAUNCH(pss::launch_corank(kt, kb[P], p.top, table, piv_dev, cnt_dev, s), "splitter launch");
+  PSS_LAUNCH(pss::launch_partition_offsets(p.top, table, sizes, offs, s), "offset scan launch");
   if (offsets)
-    PSS_TRY(hipMemcpyAsync(offsets, offs, ((size_t)n_parts + 1) * 8, hipMemcpyDeviceToDevice, s),
+    PSS_LAUNCH(hipMemcpyAsync(offsets, offs, ((size_t)n_parts + 1) * 8, hipMemcpyDeviceToDevice, s),
             "offset copy");
-  if (split) PSS_TRY(pss::launch_split_table(p.top, table, split, s), "split table launch");
-  if (sorted_blocks) PSS_TRY(pss::launch_unmap_copy(kt, kb[P], sorted_blocks, n, s), "block copy");
+  if (split) PSS_LAUNCH(pss::launch_split_table(p.top, table, split, s), "split table launch");
+  if (sorted_blocks) PSS_LAUNCH(pss::launch_unmap_copy(kt, kb[P], sorted_blocks, n, s), "block copy");
   return PSS_OK;
 }
 
 
 pss_status pss_records_workspace_bytes(const pss_ctx *ctx, pss_key_t key, uint64_t n,
                                        size_t *bytes) {
+  if (!pss::valid_enum(key, 5))
+    return fail(ctx, PSS_ERR_INVALID, "unknown key or value type");
   if (!bytes) return fail(ctx, PSS_ERR_INVALID, "null output pointer");
   RecordPlan rp;
   const pss_status st = record_plan(ctx, key, n, &rp);
@@ -1182,6 +1253,8 @@ pss_status pss_records_workspace_bytes(const pss_ctx *ctx, pss_key_t key, uint64
 pss_status pss_sort_records(pss_ctx *ctx, pss_key_t key, const void *records_in,
                             void *records_out, uint64_t n, uint32_t record_bytes,
                             uint32_t key_offset, void *ws, size_t ws_bytes, void *stream) {
+  if (!pss::valid_enum(key, 5))
+    return fail(ctx, PSS_ERR_INVALID, "unknown key or value type");
   if (!ctx) return fail(nullptr, PSS_ERR_INVALID, "null context");
   RecordPlan rp;
   pss_status st = record_plan(ctx, key, n, &rp);
@@ -1213,7 +1286,7 @@ pss_status pss_sort_records(pss_ctx *ctx, pss_key_t key, const void *records_in,
   uint32_t *perm = (uint32_t *)(w + rp.off_perm);
   {
     LaunchTimer t(ctx, "record_keys", n * ((uint64_t)record_bytes + kb + 4), s);
-    PSS_TRY(pss::launch_record_keys((int)key, records_in, n, record_bytes, key_offset, keys, idx,
+    PSS_LAUNCH(pss::launch_record_keys((int)key, records_in, n, record_bytes, key_offset, keys, idx,
                                     s),
             "record key launch");
   }
@@ -1222,7 +1295,7 @@ pss_status pss_sort_records(pss_ctx *ctx, pss_key_t key, const void *records_in,
   if (st != PSS_OK) return st;
   {
     LaunchTimer t(ctx, "record_gather", 2 * n * (uint64_t)record_bytes + 4 * n, s);
-    PSS_TRY(pss::launch_record_gather(records_in, records_out, perm, n, record_bytes, s),
+    PSS_LAUNCH(pss::launch_record_gather(records_in, records_out, perm, n, record_bytes, s),
             "record gather launch");
   }
   return PSS_OK;
@@ -1230,6 +1303,8 @@ pss_status pss_sort_records(pss_ctx *ctx, pss_key_t key, const void *records_in,
 
 pss_status pss_psrs_workspace_bytes(const pss_ctx *ctx, pss_key_t key, pss_val_t val, uint64_t n,
                                     uint32_t n_blocks, uint32_t n_parts, size_t *bytes) {
+  if (!pss::valid_enum(key, 5) || !pss::valid_enum(val, 1))
+    return fail(ctx, PSS_ERR_INVALID, "unknown key or value type");
   if (!bytes) return fail(ctx, PSS_ERR_INVALID, "null output pointer");
   if (n_blocks == 0 || n_parts == 0)
     return fail(ctx, PSS_ERR_INVALID, "PSRS needs n_blocks > 0 and n_parts > 0");
@@ -1251,6 +1326,8 @@ pss_status pss_psrs_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void 
                          void *keys_out, const uint32_t *vals_in, uint32_t *vals_out, uint64_t n,
                          uint32_t n_blocks, uint32_t n_parts, uint64_t *part_sizes, void *ws,
                          size_t ws_bytes, void *stream) {
+  if (!pss::valid_enum(key, 5) || !pss::valid_enum(val, 1))
+    return fail(ctx, PSS_ERR_INVALID, "unknown key or value type");
   PsrsPlan pp;
   pss_status st = psrs_prepare(ctx, key, val, keys_in, keys_out, vals_in, vals_out, n, n_blocks,
                                n_parts, ws, ws_bytes, &pp);
@@ -1258,7 +1335,7 @@ pss_status pss_psrs_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void 
   PSS_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   if (n == 0) {
-    if (part_sizes) PSS_TRY(hipMemsetAsync(part_sizes, 0, (size_t)n_parts * 8, s), "memset");
+    if (part_sizes) PSS_LAUNCH(hipMemsetAsync(part_sizes, 0, (size_t)n_parts * 8, s), "memset");
     return PSS_OK;
   }
   PsrsOut o;
@@ -1270,6 +1347,8 @@ pss_status pss_psrs_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, 
                               uint32_t n_blocks, uint32_t n_parts, void *sorted_blocks,
                               void *samples, void *pivots, uint64_t *split, uint64_t *offsets,
                               void *ws, size_t ws_bytes, void *stream) {
+  if (!pss::valid_enum(key, 5))
+    return fail(ctx, PSS_ERR_INVALID, "unknown key or value type");
   PsrsPlan pp;
   const char dummy = 0;  // no key output: validate keys_in against a disjoint dummy
   pss_status st = psrs_prepare(ctx, key, PSS_VAL_NONE, keys_in, n ? &dummy : nullptr, nullptr,
@@ -1280,9 +1359,9 @@ pss_status pss_psrs_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, 
   const int kt = (int)key;
   if (n == 0) {
     if (pivots && n_parts > 1)
-      PSS_TRY(hipMemsetAsync(pivots, 0, (size_t)(n_parts - 1) * pss::key_bytes(kt), s), "memset");
-    if (split) PSS_TRY(hipMemsetAsync(split, 0, (size_t)n_blocks * (n_parts + 1) * 8, s), "memset");
-    if (offsets) PSS_TRY(hipMemsetAsync(offsets, 0, ((size_t)n_parts + 1) * 8, s), "memset");
+      PSS_LAUNCH(hipMemsetAsync(pivots, 0, (size_t)(n_parts - 1) * pss::key_bytes(kt), s), "memset");
+    if (split) PSS_LAUNCH(hipMemsetAsync(split, 0, (size_t)n_blocks * (n_parts + 1) * 8, s), "memset");
+    if (offsets) PSS_LAUNCH(hipMemsetAsync(offsets, 0, ((size_t)n_parts + 1) * 8, s), "memset");
     return PSS_OK;
   }
   PsrsOut o;

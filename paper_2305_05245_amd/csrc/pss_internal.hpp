@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 
 struct pss_ctx;
 
@@ -117,12 +118,33 @@ constexpr uint32_t kMaxSegPasses = 4;
 
 // Synchronous read (and optional clear) of the device error word.
 hipError_t read_device_error(uint32_t *code, bool clear);
+// Copy of the device error word into host memory (pinned, for the copy to
+// be asynchronous) queued on stream s; the word is left as it is.
+hipError_t read_device_error_async(uint32_t *host_code, hipStream_t s);
+
+// Fault injection for tests (pss_debug_inject): kinds of operation that can be
+// made to fail.  inject_fault(kind) is called before each such operation and
+// returns true for the one operation armed to fail, which the caller then
+// reports as a failure without performing it.  Process-wide, thread-safe.
+constexpr int kInjectLaunch = 1;  // queued device work: launches, async copies
+constexpr int kInjectAlloc = 2;   // device or pinned host allocations
+bool inject_fault(int kind);
 
 // Set the calling thread's error message (pss_last_error(NULL)).
 void set_thread_error(const char *msg);
 
 // HIP device a context is bound to.
 int ctx_device(const pss_ctx *ctx);
+
+// Whether an enum argument, which a C caller may have set to any int, holds
+// one of 0..max.  Its bits are read as an int and never loaded as the C++
+// enum, since loading a value outside the enumerators is undefined in C++.
+template <typename E> inline bool valid_enum(const E &e, int max) {
+  static_assert(sizeof(E) == sizeof(int), "enum held as int");
+  int v;
+  std::memcpy(&v, &e, sizeof v);
+  return v >= 0 && v <= max;
+}
 
 // key-type codes (same numbering as pss_key_t)
 inline int key_bytes(int kt) { return (kt == 0 || kt == 1 || kt == 4) ? 4 : 8; }

@@ -2431,19 +2431,6 @@ hipError_t dispatch_kt(int kt, F &&f) {
 }  // namespace
 
 // ------------------------------------------------------------ launchers ---
-RunGeom sample_geom(const RunGeom &g) {
-  RunGeom s = g;
-  const uint64_t nseg = (g.n + g.seg_len - 1) / g.seg_len;
-  const uint64_t last = g.n - (nseg - 1) * g.seg_len;
-  s.seg_len = g.seg_len >> kSampleLog2;
-  s.n = (nseg - 1) * s.seg_len + (last >> kSampleLog2);
-  s.run_len = g.run_len >> kSampleLog2;
-  s.group_len = g.group_len >> kSampleLog2;
-  s.part_len = kPart;
-  s.rows_per_group = (uint32_t)((s.group_len + kPart - 1) / kPart) + 1;
-  return s;
-}
-
 namespace {
 template <int KT, bool KV, int THREADS>
 hipError_t go_tile(const void *in, const uint32_t *vin, const TileArgs<typename Key<KT>::U> &ta,
@@ -2806,6 +2793,11 @@ hipError_t read_device_error(uint32_t *code, bool clear) {
   const uint32_t zero = 0;
   return hipMemcpyToSymbol(HIP_SYMBOL(g_device_error), &zero, sizeof(uint32_t), 0,
                            hipMemcpyHostToDevice);
+}
+
+hipError_t read_device_error_async(uint32_t *host_code, hipStream_t s) {
+  return hipMemcpyFromSymbolAsync(host_code, HIP_SYMBOL(g_device_error), sizeof(uint32_t), 0,
+                                  hipMemcpyDeviceToHost, s);
 }
 
 hipError_t launch_unmap_copy(int kt, const void *src, void *dst, uint64_t n, hipStream_t s) {

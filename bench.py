@@ -13,13 +13,18 @@ launch (every key read once and written once: 16 bytes per int64 key) divided
 by its mean launch time, timed with HIP events recorded by the library on the
 stream the kernel runs on, during the timed steps.  `traffic` is the kernel's
 measured HBM bytes per launch from the committed counter summary, while the
-kernel source still matches it.  The CPU baseline is the sequential oracle
-timed on a bounded sample on the host.
+kernel source still matches it.  sort_roofline reports the whole sort against
+the method's two data passes (32 bytes per int64 key), timed by the host
+clock.  The CPU baseline is the sequential oracle on the full input, pinned to
+one core, beside the oracle's steps run by OpenMP threads on the host's cores
+(child processes that touch no GPU).
 
-Two more legs are added to the line: "batched" (4096 int64 arrays of
-log-uniform sizes sorted by one captured graph, against one sort per array)
-and "serving" (Poisson arrivals of u64 key + u32 value requests into the
-library's serving loop: p50 / p99 latency and keys/s).
+More legs are added to the line: "batched" (4096 int64 arrays of log-uniform
+sizes sorted by one captured graph, against one sort per array), "serving"
+(Poisson arrivals of u64 key + u32 value requests into the library's serving
+loop: p50 / p99 latency and keys/s, beside one sort per request on one
+stream), and the key-value, distribution, record, six-input and splitting
+legs.
 """
 from __future__ import annotations
 
@@ -111,21 +116,88 @@ def time_sort(pss, torch, keys_dev, out, ws, steps: int, warmup: int, profile: b
     return wall, evs[0].elapsed_time(evs[-1]) / 1e3, kernels, per_step
 
 
-def cpu_baseline(log2n: int = 26):
-    """The oracle as it stands (sequential C, one thread) on a bounded sample
-    of the same workload: 2^log2n uniform int64 keys, n_B = n_P = 48."""
+CPU_BASELINE_LOG2N = 28
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_child(mode: str, log2n: int) -> int:
+    """Child process of the CPU baseline (touches no GPU): times the oracle
+    on 2^log2n uniform int64 keys (seed 2) and prints one JSON object.
+    mode "oracle": the sequential oracle pinned to the first allowed core,
+    n_B = n_P = 16, one run.  mode "host": the oracle's steps with their
+    loops over blocks, pivots and partitions on T OpenMP threads (T as the
+    OpenMP runtime sets it: OMP_NUM_THREADS where the environment gives the
+    process its share of the host, else every core), n_B = n_P = T as in the
+    paper's setting, mean of 3 runs."""
+    import numpy as np
+
     import oracle
     import workloads as W
 
+    cores = sorted(os.sched_getaffinity(0))
+    if mode == "oracle":
+        os.sched_setaffinity(0, {cores[0]})
     n = 1 << log2n
     keys = W.uniform_i64(n, seed=2)
-    oracle.build()
-    t0 = time.perf_counter()
-    oracle.pses(keys, 48, 48)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt / 1e9, "unit": "GKeys/s", "cores": 1, "kind": "oracle",
-            "sample": f"2^{log2n} uniform int64 keys (seed 2), n_B = n_P = 48, single thread, "
-                      f"{dt:.1f} s"}
+    res = {"n": n, "cpu_model": _cpu_model()}
+    if mode == "oracle":
+        oracle.build()
+        t0 = time.perf_counter()
+        out = oracle.pses(keys, 16, 16).keys
+        dt = time.perf_counter() - t0
+        res.update(seconds=dt, cores=1, core=cores[0], runs=1)
+    else:
+        oracle.build_host_parallel()
+        t_threads = oracle.host_parallel_threads()
+        runs = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            out = oracle.host_parallel_pses(keys, t_threads, t_threads)
+            runs.append(time.perf_counter() - t0)
+        dt = float(np.mean(runs))
+        res.update(seconds=dt, cores=t_threads, runs=3, run_seconds=[round(r, 3) for r in runs])
+    res["ascending"] = bool(np.all(out[1:] >= out[:-1]))
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def cpu_baseline(log2n: int = CPU_BASELINE_LOG2N) -> dict:
+    """The oracle as it stands timed on this machine's host, in child processes
+    that touch no GPU: sequentially on one pinned core, and as the host
+    baseline (its loops over blocks, pivots and partitions on all allowed
+    cores, n_B = n_P = cores).  Input generation is not timed."""
+    import subprocess
+
+    def child(mode):
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-child", mode,
+                            "--log2n", str(log2n)], capture_output=True, text=True, timeout=900)
+        if r.returncode != 0:
+            raise RuntimeError(f"CPU baseline ({mode}) failed:\n{r.stderr[-2000:]}")
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    seq = child("oracle")
+    par = child("host")
+    n = seq["n"]
+    assert seq["ascending"] and par["ascending"]
+    return {"value": n / seq["seconds"] / 1e9, "unit": "GKeys/s", "cores": 1, "kind": "oracle",
+            "sample": f"the full 2^{log2n} uniform int64 keys (seed 2) of the single-sort "
+                      f"workload, sequential oracle, n_B = n_P = 16, pinned to core "
+                      f"{seq['core']}, one run of {seq['seconds']:.1f} s",
+            "cpu_model": seq["cpu_model"],
+            "host_parallel": {
+                "value": n / par["seconds"] / 1e9, "unit": "GKeys/s", "cores": par["cores"],
+                "kind": "oracle steps 1-4 with their loops over blocks, pivots and partitions "
+                        "on OpenMP threads, n_B = n_P = threads",
+                "seconds_mean_of_3": round(par["seconds"], 3), "run_seconds": par["run_seconds"]}}
 
 
 def bench_key_value(pss, torch, log2n: int, steps: int, warmup: int) -> dict:
@@ -466,6 +538,7 @@ def bench_batched(pss, torch, steps: int, warmup: int) -> dict:
     t_each = (time.perf_counter() - t0) / reps
     same = bool(torch.equal(out, out2))
     graph.close()
+    assert pss.device_check(0) == 0
     return {"workload": "4096 int64 arrays, sizes round(2^U), U~Uniform[6,20] (seed 12), "
                         "uniform keys (seed 13)",
             "total_keys": total, "graph_ms": round(t_graph * 1e3, 3),
@@ -485,11 +558,19 @@ def bench_serving(torch, _unused: float, n_req: int = 20000, warm_req: int = 200
     requests uniform u64 keys and half keys in {0, 1, 2} (seed 16), each with
     its uint32 input index as value, against a server holding a 64 GB budget.
     The offered load is 0.7 x the server's own saturated throughput, measured
-    first by a closed-loop burst of the same request mix."""
+    first by a closed-loop burst of the same request mix.
+
+    The same request streams are then run as one pss_sort per request on one
+    stream (the launch-per-array baseline): its saturated throughput, and its
+    latency from arrival to completion (HIP events on the stream, aligned to
+    the host clock) under the same arrivals.  Both modes' outputs of a sample
+    of requests are compared with the oracle and with each other."""
     import numpy as np
 
+    import oracle
     import workloads as W
-    from paper_2305_05245_amd import _lib
+    import paper_2305_05245_amd as pss
+    from paper_2305_05245_amd import _context, _lib
     from paper_2305_05245_amd.serving import Server
 
     hi = 1 << 24
@@ -516,22 +597,25 @@ def bench_serving(torch, _unused: float, n_req: int = 20000, warm_req: int = 200
     pu, pd, pv = pool_u.data_ptr(), pool_d.data_ptr(), idx.data_ptr()
     rk, rv = ring_k.data_ptr(), ring_v.data_ptr()
 
-    def drive(arrivals, sizes, dup, starts, t0_ns, reset_at=-1):
+    def wait_ok(ticket):
+        lib.pss_wait(hsrv, ticket, ctypes.byref(st))
+        if st.value != _lib.OK:
+            raise _lib.PssError(st.value, "request failed")
+
+    def drive(arrivals, sizes, dup, starts, t0_ns):
         """Submit every request at its arrival time (busy wait); outputs go to
-        a ring that waits for the oldest request before reusing its space."""
+        a ring that waits for the oldest request before reusing its space.
+        Returns once every request has completed."""
         outstanding = collections.deque()  # (ticket, ring start, ring end)
         head = 0
         late = 0
         for j in range(len(sizes)):
-            if j == reset_at:
-                srv.reset_stats()
-                late = 0
             n = sizes[j]
             if head + n > ring_len:
                 head = 0
             while outstanding and (outstanding[0][1] < head + n and head < outstanding[0][2]
                                    or len(outstanding) > 60000):
-                lib.pss_wait(hsrv, outstanding.popleft()[0], ctypes.byref(st))
+                wait_ok(outstanding.popleft()[0])
             due = t0_ns + int(arrivals[j] * 1e9) if arrivals is not None else 0
             if due:
                 now = time.monotonic_ns()
@@ -549,10 +633,51 @@ def bench_serving(torch, _unused: float, n_req: int = 20000, warm_req: int = 200
             outstanding.append((tk.value, head, head + n))
             head += n
         while outstanding:
-            lib.pss_wait(hsrv, outstanding.popleft()[0], ctypes.byref(st))
-            if st.value != _lib.OK:
-                raise _lib.PssError(st.value, "request failed")
+            wait_ok(outstanding.popleft()[0])
         return late
+
+    # --- one pss_sort per request on one stream ---------------------------
+    ctx = _context(0)
+    stream = torch.cuda.current_stream()
+    hs = stream.cuda_stream
+    pws = torch.empty(_lib.workspace_bytes(_lib.U64, _lib.VAL_U32, hi), dtype=torch.uint8,
+                      device="cuda")
+    wp, wn = pws.data_ptr(), pws.numel()
+
+    def per_request(arrivals, sizes, dup, starts, t0_ns):
+        """Launch each request's sort at its arrival time (or back to back
+        with arrivals None).  Completion times come from an event recorded
+        after each sort, read against a reference event recorded on the idle
+        stream at a known host time.  Returns (latencies in ms, wall s)."""
+        torch.cuda.synchronize()
+        ref = torch.cuda.Event(enable_timing=True)
+        ref.record(stream)
+        torch.cuda.synchronize()
+        ref_ns = time.monotonic_ns()
+        evs = []
+        head = 0
+        t_start = time.perf_counter()
+        for j in range(len(sizes)):
+            n = sizes[j]
+            if head + n > ring_len:
+                head = 0   # one stream: earlier sorts are done before these writes run
+            due = t0_ns + int(arrivals[j] * 1e9) if arrivals is not None else 0
+            while due and time.monotonic_ns() < due:
+                pass
+            base = (pd if dup[j] else pu) + starts[j] * 8
+            ctx.sort(_lib.U64, _lib.VAL_U32, base, rk + head * 8, pv, rv + head * 4, n, 0, 0,
+                     wp, wn, hs)
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(stream)
+            evs.append((ev, due if due else ref_ns))
+            head += n
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        lat = [max(0.0, ref.elapsed_time(ev) - (a - ref_ns) * 1e-6) for ev, a in evs]
+        return np.array(lat), wall
+
+    def pct(a, p):
+        return float(np.sort(a)[max(0, int(np.ceil(p * a.size)) - 1)])
 
     try:
         # saturated throughput: a closed-loop burst of the same mix
@@ -564,15 +689,46 @@ def bench_serving(torch, _unused: float, n_req: int = 20000, warm_req: int = 200
         sat = srv.stats()
         sat_wall = time.perf_counter() - t0
         capacity = sum(sizes) / sat_wall
+        per_request(None, sizes[:300], dup, starts, 0)
+        _, pr_sat_wall = per_request(None, sizes, dup, starts, 0)
+        pr_capacity = sum(sizes) / pr_sat_wall
         mean_size = float(np.mean(sizes))
         rate = 0.7 * capacity / mean_size
-        arr, sizes, dup, starts = mix(warm_req + n_req, rate, 0)
+        # warm-up requests first, all completed before the counters restart
+        warr, wsizes, wdup, wstarts = mix(warm_req, rate, 50)
+        drive(warr, wsizes, wdup, wstarts, time.monotonic_ns() + 2_000_000)
+        srv.reset_stats()
+        arr, sizes, dup, starts = mix(n_req, rate, 0)
         t0_ns = time.monotonic_ns() + 5_000_000
-        warm_end = arr[warm_req - 1]
-        # one schedule: the counters restart when the first measured request
-        # arrives (warm-up requests still in flight then are counted too)
-        late = drive(arr, sizes, dup, starts, t0_ns, reset_at=warm_req)
+        late = drive(arr, sizes, dup, starts, t0_ns)
         s = srv.stats()
+        assert s["completed"] == n_req and s["failed"] == 0, s
+        assert s["budget_in_use"] == 0 and s["queued"] == 0, s
+        # the same arrivals, one sort per request
+        lat, pr_wall = per_request(arr, sizes, dup, starts, time.monotonic_ns() + 5_000_000)
+        # keys completed over the time from the first arrival to the last
+        # completion (the server's own definition)
+        done_s = np.asarray(arr) + lat * 1e-3
+        pr_keys_per_s = sum(sizes) / max(float(done_s.max() - arr[0]), 1e-9)
+
+        # correctness of both modes on a sample of the same requests
+        sample = [j for j in range(0, n_req, max(1, n_req // 16))][:16]
+        checked = 0
+        for j in sample:
+            n = sizes[j]
+            src = (pool_d if dup[j] else pool_u)[starts[j]:starts[j] + n]
+            a_k, a_v = torch.empty_like(src), torch.empty(n, dtype=torch.int32, device="cuda")
+            b_k, b_v = torch.empty_like(src), torch.empty(n, dtype=torch.int32, device="cuda")
+            wait_ok(srv.submit(src, a_k, idx[:n], a_v, key_type="u64"))
+            pss.sort(src, idx[:n], key_type="u64", out=b_k, vals_out=b_v)
+            torch.cuda.synchronize()
+            keys_h = src.cpu().numpy().view(np.uint64)
+            ref = oracle.pses(keys_h, 4, 4, vals=np.arange(n, dtype=np.uint32))
+            assert np.array_equal(a_k.cpu().numpy().view(np.uint64), ref.keys), j
+            assert np.array_equal(a_v.cpu().numpy().view(np.uint32), ref.vals), j
+            assert torch.equal(a_k, b_k) and torch.equal(a_v, b_v), j
+            checked += 1
+        assert pss.device_check(0) == 0
     finally:
         srv.close()
     return {"workload": "Poisson arrivals (seed 14), lognormal sizes median 2^16 sigma 1.5 "
@@ -588,7 +744,15 @@ def bench_serving(torch, _unused: float, n_req: int = 20000, warm_req: int = 200
             "mean_ms": round(s["latency_mean_ms"], 4), "max_ms": round(s["latency_max_ms"], 4),
             "batches": s["batches"], "mean_batch_requests": round(s["mean_batch_requests"], 2),
             "completed": s["completed"], "late_submissions": late,
-            "warmup_end_s": round(float(warm_end), 3)}
+            "per_request_baseline": {
+                "what": "one pss_sort (stable key-value, automatic plan) per request, launched "
+                        "at its arrival on one stream",
+                "saturated_gkeys_per_s": round(pr_capacity / 1e9, 3),
+                "gkeys_per_s": round(pr_keys_per_s / 1e9, 3),
+                "p50_ms": round(pct(lat, 0.5), 4), "p99_ms": round(pct(lat, 0.99), 4),
+                "max_ms": round(float(lat.max()), 4)},
+            "server_vs_per_request_saturated": round(capacity / pr_capacity, 2),
+            "oracle_checked_requests": checked}
 
 
 def main() -> int:
@@ -614,11 +778,14 @@ def main() -> int:
     ap.add_argument("--leg", choices=("batched", "serving", "key_value", "splitting", "records",
                                       "paper_inputs", "distributions"),
                     help="run only this leg and print its JSON object (for profiling)")
+    ap.add_argument("--cpu-child", choices=("oracle", "host"), help=argparse.SUPPRESS)
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a plain device-to-device copy of the keys (bandwidth and "
                          "counter calibration), print its line and exit")
     args = ap.parse_args()
 
+    if args.cpu_child:
+        return cpu_child(args.cpu_child, args.log2n)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(sharding across GPUs is described in the design notes, not implemented)", file=sys.stderr)
@@ -699,17 +866,35 @@ def main() -> int:
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
     roofline = {
         "bound": "hbm",
-        "kernel": dom_name,
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": measured_traffic(dom_name, args.log2n, args.dist),
+        "scope": "dominant kernel family, one launch (not the whole sort: see sort_roofline)",
+        "kernel": dom_name,
+        "timer": "HIP events the library records around each launch on the launch stream, "
+                 "during the timed steps",
         "bytes_per_launch": per_launch_bytes,
         "mean_launch_ms": round(per_launch_ms, 4),
     }
-    # whole-sort view against the method's 2 data passes (16 B/key each)
+    # whole sort against the method's 2 data passes (step 1 and step 4 each
+    # read and write every key once: 2 x 2 x 8 B per int64 key)
     algo_bytes = 2 * 2 * 8 * n
+    step_s = wall / args.steps
+    sweeps = int(plan.get("hbm_passes", 0))
+    sort_roofline = {
+        "bound": "hbm",
+        "passes": 2,
+        "algorithmic_bytes": algo_bytes,
+        "achieved": round(algo_bytes / step_s / 1e9, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(algo_bytes / step_s / 1e9 / HBM_PEAK_GBS, 4),
+        "timer": "host wall clock over the timed steps, bracketed by device synchronisation",
+        "sweeps_made": sweeps,
+        "frac_of_sweeps_made": round(sweeps * 2 * 8 * n / step_s / 1e9 / HBM_PEAK_GBS, 4),
+    }
     line = {
         "metric": METRIC,
         "value": round(gkeys, 3),
@@ -731,7 +916,7 @@ def main() -> int:
             "plan": plan,
         },
         "roofline": roofline,
-        "sort_roofline_2pass_frac": round(algo_bytes / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+        "sort_roofline": sort_roofline,
         "hip_event_ms_per_step": round(ev_s / args.steps * 1e3, 4),
         "step_ms": {"mean": round(float(np.mean(per_step)), 4),
                     "median": round(float(np.median(per_step)), 4),

@@ -66,6 +66,53 @@ def build(force: bool = False) -> str:
     return _LIB_PATH
 
 
+_HP_SRC = os.path.join(_HERE, "pses_host_parallel.c")
+_HP_PATH = os.path.join(_HERE, "libhostpar.so")
+_hp = None
+
+
+def build_host_parallel(force: bool = False) -> str:
+    """Compile the OpenMP host baseline (pses_host_parallel.c, which includes
+    the oracle's source) into libhostpar.so."""
+    with _lock:
+        newest = max(os.path.getmtime(_HP_SRC), os.path.getmtime(_SRC))
+        if force or not os.path.exists(_HP_PATH) or os.path.getmtime(_HP_PATH) < newest:
+            tmp = _HP_PATH + f".tmp{os.getpid()}"
+            subprocess.check_call(
+                ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra",
+                 "-o", tmp, _HP_SRC]
+            )
+            os.replace(tmp, _HP_PATH)
+    return _HP_PATH
+
+
+def host_parallel_pses(keys: np.ndarray, n_blocks: int, n_parts: int) -> np.ndarray:
+    """The host baseline: the oracle's steps with their loops over blocks,
+    pivots and partitions shared among OpenMP threads (keys only)."""
+    global _hp
+    if _hp is None:
+        build_host_parallel()
+        lib = ctypes.CDLL(_HP_PATH)
+        lib.host_parallel_pses.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p,
+                                           ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
+        lib.host_parallel_pses.restype = ctypes.c_int
+        lib.host_parallel_threads.restype = ctypes.c_int
+        _hp = lib
+    keys = np.ascontiguousarray(keys)
+    name = {np.dtype(v[1]): k for k, v in DTYPES.items()}[keys.dtype]
+    out = np.empty_like(keys)
+    rc = _hp.host_parallel_pses(dtype_code(name), keys.size, keys.ctypes.data_as(ctypes.c_void_p),
+                                n_blocks, n_parts, out.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise RuntimeError(f"host_parallel_pses failed: {rc}")
+    return out
+
+
+def host_parallel_threads() -> int:
+    host_parallel_pses(np.zeros(1, dtype=np.int64), 1, 1)  # loads the library
+    return int(_hp.host_parallel_threads())
+
+
 def bind(path: str):
     """ctypes handle for a compiled oracle at `path` (the default build, or a
     mutated copy compiled by the tests that check the pins catch mistakes)."""

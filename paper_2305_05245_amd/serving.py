@@ -36,20 +36,17 @@ class Server:
                                               ctypes.byref(h)))
         self.handle = h
         self._live: dict[int, tuple] = {}
-        self._req = _lib.Request()
-        self._ticket = ctypes.c_uint64()
-        self._status = ctypes.c_int()
-        self._done = ctypes.c_int()
 
     # -- requests -------------------------------------------------------
     def submit_raw(self, key: int, val: int, keys_in: int, keys_out: int, vals_in: int,
                    vals_out: int, n: int, arrival_ns: int = 0) -> int:
         """Submit by device address (the caller keeps the memory alive)."""
-        r = self._req
+        r = _lib.Request()
         r.key, r.val, r.keys_in, r.keys_out = key, val, keys_in or None, keys_out or None
         r.vals_in, r.vals_out, r.n, r.arrival_ns = vals_in or None, vals_out or None, n, arrival_ns
-        _lib.check(self.lib.pss_submit(self.handle, ctypes.byref(r), ctypes.byref(self._ticket)))
-        return int(self._ticket.value)
+        ticket = ctypes.c_uint64()
+        _lib.check(self.lib.pss_submit(self.handle, ctypes.byref(r), ctypes.byref(ticket)))
+        return int(ticket.value)
 
     def submit(self, keys: torch.Tensor, out: torch.Tensor, vals: torch.Tensor | None = None,
                vals_out: torch.Tensor | None = None, key_type: str | int | None = None,
@@ -79,11 +76,11 @@ class Server:
         return tk
 
     def poll(self, ticket: int) -> tuple[bool, int | None]:
-        _lib.check(self.lib.pss_poll(self.handle, ticket, ctypes.byref(self._done),
-                                     ctypes.byref(self._status)))
-        if self._done.value:
+        done, status = ctypes.c_int(), ctypes.c_int()
+        _lib.check(self.lib.pss_poll(self.handle, ticket, ctypes.byref(done), ctypes.byref(status)))
+        if done.value:
             self._live.pop(ticket, None)
-            return True, int(self._status.value)
+            return True, int(status.value)
         return False, None
 
     def wait(self, ticket: int) -> int:

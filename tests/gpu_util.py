@@ -28,16 +28,35 @@ def from_device(t, dtype) -> np.ndarray:
     return t.cpu().numpy().view(dtype)
 
 
+POISON = 0xAB
+
+
+def poisoned_workspace(nbytes: int):
+    """A device workspace whose every byte is 0xAB, so that a kernel reading
+    scratch memory it has not written first yields a mismatch instead of
+    whatever an earlier call left there."""
+    import torch
+
+    return torch.full((max(int(nbytes), 256),), POISON, dtype=torch.uint8, device="cuda")
+
+
 def gpu_sort(keys: np.ndarray, vals: np.ndarray | None = None, n_blocks: int = 0, n_parts: int = 0):
+    """Sort on the device through the C ABI, with a poisoned workspace; the
+    device error word must stay clear."""
     import torch
 
     import paper_2305_05245_amd as pss
+    from paper_2305_05245_amd import _lib
 
     kt = KEY_OF_DTYPE[keys.dtype]
     dk = to_device(keys)
     dv = to_device(vals.astype(np.uint32)) if vals is not None else None
-    out, vout = pss.sort(dk, dv, n_blocks=n_blocks, n_parts=n_parts, key_type=kt)
+    ws = poisoned_workspace(_lib.workspace_bytes(_lib.KEY_NAMES[kt],
+                                                 _lib.VAL_U32 if vals is not None else _lib.VAL_NONE,
+                                                 keys.size, n_blocks, n_parts))
+    out, vout = pss.sort(dk, dv, n_blocks=n_blocks, n_parts=n_parts, key_type=kt, workspace=ws)
     torch.cuda.synchronize()
+    assert pss.device_check() == 0, "device error word set"
     ko = from_device(out, keys.dtype)
     vo = from_device(vout, np.uint32) if vout is not None else None
     return ko, vo

@@ -2,17 +2,20 @@
 
 Small and medium sizes compare every output element with the oracle (and, in
 the paper's single-level mode, every intermediate: sorted blocks, pivots P_k,
-counts c_k, split table, offsets).  Full-size configurations (2^28 int64,
-2^27 float64) are checked by properties that pin the result at any size:
-ascending order, equal multiset of bit patterns, and sampled ranks computed one
-by one by the oracle's direct count.
+counts c_k, split table, offsets).  The full-size configurations (2^28 int64,
+2^27 float64, five distributions each) are compared element by element with
+their exact sorted output: the oracle's at full N for uniform int64 and for
+normal floats with specials, closed forms or numpy's sort of the order bits
+for the others, plus sampled ranks counted one by one by the oracle.  Every
+sort runs on a workspace poisoned with 0xAB and checks the device error word.
 """
 import numpy as np
 import pytest
 
 import oracle
 import workloads as W
-from gpu_util import announce, gpu_sort, is_sorted, multiset_signature, from_device, to_device, KEY_OF_DTYPE
+from gpu_util import (KEY_OF_DTYPE, announce, from_device, gpu_sort, is_sorted, order_bits,
+                      to_device)
 
 pytestmark = pytest.mark.gpu
 
@@ -168,18 +171,6 @@ def test_paper_key_value():
 
 
 # --------------------------------------------------------------- full size
-def check_full(keys, samples=8, seed=0):
-    announce("full", keys.dtype.name, keys.size)
-    got, _ = gpu_sort(keys)
-    assert got.size == keys.size
-    assert is_sorted(got), "not ascending"
-    assert multiset_signature(got) == multiset_signature(keys), "not a permutation"
-    rng = np.random.default_rng(seed)
-    for r in rng.integers(0, keys.size, size=samples).tolist() + [0, keys.size - 1]:
-        lt, le = oracle.rank_counts(keys, got[r])
-        assert lt <= r < le, f"rank {r} holds the wrong key"
-
-
 C2 = {
     "uniform": lambda n: W.uniform_i64(n, seed=2),
     "mod1000": lambda n: W.mod1000_i64(n, seed=3),
@@ -196,14 +187,56 @@ C3 = {
 }
 
 
+def expected_full(dist: str, keys: np.ndarray) -> np.ndarray:
+    """The exact sorted output of a full-size input.
+
+    uniform int64 (2^28) and normal with specials (2^27 f64) come from the
+    oracle, element by element.  The inputs that are permutations of 0..N-1
+    (sorted, reverse, 1% transpositions) sort to 0..N-1; all-equal sorts to
+    itself; organ pipe min(i, N-1-i) holds each value below N/2 twice (N
+    even); mod 1000 sorts to each value v repeated as often as it occurs
+    (counted by bincount).  The two remaining float inputs (uniform [0,1),
+    normal) sort to their order bits sorted by numpy, mapped back to the
+    same bits, so the multiset comparison is exact."""
+    n = keys.size
+    if dist in ("uniform", "normal_specials"):
+        return oracle.pses(keys, 16, 16).keys
+    if dist in ("sorted", "reverse", "swapped1pct"):
+        return np.arange(n, dtype=np.int64)
+    if dist == "allequal":
+        return keys.copy()
+    if dist == "organpipe":
+        assert n % 2 == 0
+        return np.repeat(np.arange(n // 2, dtype=np.float64), 2)
+    if dist == "mod1000":
+        return np.repeat(np.arange(1000, dtype=np.int64), np.bincount(keys, minlength=1000))
+    # uniform01, normal: sort the totalOrder bits and map them back
+    o = np.sort(order_bits(keys))
+    return np.where(o < 0, o ^ np.int64(0x7FFFFFFFFFFFFFFF), o).view(np.float64)
+
+
+def check_full(dist: str, keys: np.ndarray, samples: int = 4, seed: int = 0):
+    announce("full", dist, keys.dtype.name, keys.size)
+    got, _ = gpu_sort(keys)
+    assert got.size == keys.size
+    assert is_sorted(got), "not ascending"
+    exp = expected_full(dist, keys)
+    assert same_bits(got, exp), "differs from the exact sorted output"
+    # independent of the above: sampled ranks by the oracle's direct count
+    rng = np.random.default_rng(seed)
+    for r in rng.integers(0, keys.size, size=samples).tolist() + [0, keys.size - 1]:
+        lt, le = oracle.rank_counts(keys, got[r])
+        assert lt <= r < le, f"rank {r} holds the wrong key"
+
+
 @pytest.mark.parametrize("dist", list(C2))
 def test_full_size_int64_2p28(dist):
-    check_full(C2[dist](1 << 28))
+    check_full(dist, C2[dist](1 << 28))
 
 
 @pytest.mark.parametrize("dist", list(C3))
 def test_full_size_float64_2p27(dist):
-    check_full(C3[dist](1 << 27))
+    check_full(dist, C3[dist](1 << 27))
 
 
 @pytest.mark.parametrize("dist", list(C2))

@@ -1,14 +1,16 @@
 """GPU parity of the batched segmented sort: every segment of the output must
 equal the oracle's sort of that segment alone, bit for bit (stable payload
 where given), for every tile class and tuning; at the full batched size
-(4096 segments, 2^6..2^20 keys each) per-segment order, per-segment multisets
-and sampled segments checked against the oracle."""
+(4096 segments, 2^6..2^20 keys each) every segment against numpy's sort of
+it and sampled segments against the oracle; segments above 2^23 keys (three
+merge passes) against the oracle.  Every call runs on a workspace poisoned
+with 0xAB and checks the device error word."""
 import numpy as np
 import pytest
 
 import oracle
 import workloads as W
-from gpu_util import KEY_OF_DTYPE, announce, from_device, multiset_signature, order_bits, to_device
+from gpu_util import KEY_OF_DTYPE, announce, from_device, poisoned_workspace, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -49,16 +51,26 @@ def oracle_segmented(keys, offs, vals=None):
 
 
 def gpu_segmented(keys, offs, vals=None, tuning=None, max_seg_len=None):
+    """Segmented sort on the device with a poisoned workspace; the device
+    error word must stay clear."""
     import torch
 
     import paper_2305_05245_amd as pss
+    from paper_2305_05245_amd import _lib
 
     dk = to_device(keys)
     dv = to_device(vals.astype(np.uint32)) if vals is not None else None
     d_offs = torch.from_numpy(offs.astype(np.int64)).cuda()
-    out, vout = pss.segmented_sort(dk, d_offs, dv, key_type=KEY_OF_DTYPE[keys.dtype],
-                                   tuning=tuning, max_seg_len=max_seg_len)
+    kt = KEY_OF_DTYPE[keys.dtype]
+    vt = _lib.VAL_U32 if vals is not None else _lib.VAL_NONE
+    tu = pss._resolve_tuning(tuning, _lib.KEY_NAMES[kt], vt, keys.size, offs.size - 1,
+                             max_seg_len if max_seg_len is not None else
+                             (int(np.max(np.diff(offs))) if offs.size > 1 else 0))
+    ws = poisoned_workspace(_lib.segmented_workspace_bytes(_lib.KEY_NAMES[kt], vt, keys.size,
+                                                           offs.size - 1, tu))
+    out, vout = pss.segmented_sort(dk, d_offs, dv, key_type=kt, tuning=tu, workspace=ws)
     torch.cuda.synchronize()
+    assert pss.device_check() == 0, "device error word set"
     return from_device(out, keys.dtype), (from_device(vout, np.uint32) if vout is not None else None)
 
 
@@ -144,25 +156,46 @@ def test_segmented_loguniform_batch_exact():
 
 
 def test_segmented_full_batch_4096_segments():
-    """4096 segments of round(2^U), U ~ U[6, 20] int64 keys (about 4.4e8 keys)."""
+    """4096 segments of round(2^U), U ~ U[6, 20] int64 keys (about 4.4e8 keys):
+    every segment equals numpy's sort of that segment's input (int64 keys:
+    the exact sorted output), and sampled segments equal the oracle's."""
     sizes = W.segment_sizes_loguniform(4096, 6.0, 20.0, seed=12)
     offs = W.segment_offsets(sizes).astype(np.int64)
     n = int(offs[-1])
     keys = W.uniform_i64(n, seed=13)
     announce("segmented-full", n)
     got, _ = gpu_segmented(keys, offs)
-    o = order_bits(got)
-    starts = np.zeros(n, dtype=bool)
-    starts[offs[:-1][sizes > 0]] = True
-    ok = (o[1:] >= o[:-1]) | starts[1:]
-    assert bool(np.all(ok)), "a segment is not ascending"
-    rng = np.random.default_rng(0)
-    for i in rng.choice(offs.size - 1, size=24, replace=False).tolist() + [int(np.argmax(sizes))]:
+    for i in range(offs.size - 1):
         lo, hi = int(offs[i]), int(offs[i + 1])
-        assert multiset_signature(got[lo:hi]) == multiset_signature(keys[lo:hi]), i
+        assert np.array_equal(got[lo:hi], np.sort(keys[lo:hi])), i
+    rng = np.random.default_rng(0)
+    for i in rng.choice(offs.size - 1, size=8, replace=False).tolist():
+        lo, hi = int(offs[i]), int(offs[i + 1])
         if hi - lo <= (1 << 18):
             r = oracle.pses(keys[lo:hi], 4, 4)
             assert same(got[lo:hi], r.keys), i
+
+
+@pytest.mark.parametrize("kv", [False, True], ids=["keys", "key-value"])
+def test_segmented_three_merge_passes(kv):
+    """Segments above 2^23 keys take three merge passes (2^11+ tiles of 8192
+    keys) with the segment's data ending in the output or the workspace by
+    the parity of its own pass count: segments of 2^23 + 1 and 2^24 keys (three
+    passes), 2^23 (two), 2^20 + 3 (two) and short ones (none or one), mixed,
+    against the oracle segment by segment."""
+    sizes = np.array([1000, (1 << 23) + 1, 5, (1 << 20) + 3, 1 << 24, 8193, 1 << 23, 0, 77],
+                     dtype=np.int64)
+    offs = np.zeros(sizes.size + 1, dtype=np.int64)
+    np.cumsum(sizes, out=offs[1:])
+    keys = np.concatenate([W.request_keys(int(s), i % 2 == 1, seed=40 + i)
+                           for i, s in enumerate(sizes)]).view(np.uint64)
+    vals = np.arange(keys.size, dtype=np.uint32) if kv else None
+    announce("segmented-3-pass", "kv" if kv else "keys", int(offs[-1]))
+    gk, gv = gpu_segmented(keys, offs, vals)
+    ek, ev = oracle_segmented(keys, offs, vals)
+    assert same(gk, ek)
+    if kv:
+        assert np.array_equal(gv, ev)
 
 
 def test_segmented_invalid_offsets_reported():

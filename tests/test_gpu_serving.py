@@ -1,7 +1,9 @@
 """Serving loop (pss_server_*): every request's result is the same whether it
-is sorted alone or batched with others, and equals the stable sort of its
-input; budget admission, cancellation and the error paths behave as
-documented."""
+is sorted alone or batched with others, and equals the oracle's sort of its
+input, over the serving workload's whole size range (2^10 to 2^24 keys);
+requests that arrive while the workers are busy share batches; a failed
+launch fails only its own batch; budget admission, cancellation and the
+error paths behave as documented."""
 from __future__ import annotations
 
 import time
@@ -9,29 +11,36 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 import workloads as W
-from gpu_util import announce, order_bits, to_device
+from gpu_util import announce, to_device
 
 pytestmark = pytest.mark.gpu
 
 
-def _stable(keys: np.ndarray):
-    o = np.argsort(order_bits(keys), kind="stable")
-    return keys[o], o.astype(np.uint32)
+def _oracle(keys: np.ndarray, vals: np.ndarray | None):
+    """The request's exact result: the oracle's sort (stable by input index)."""
+    nb = 4 if keys.size > 64 else 1
+    r = oracle.pses(keys, nb, nb, vals=vals)
+    return r.keys, r.vals
 
 
 def _mixed_requests(n_req: int, seed: int):
-    """The serving workload's shape (lognormal sizes, half uniform and half
-    duplicate-heavy u64 keys with their input index as value), sizes clipped
-    to 2^18 so the test stays short, plus keys-only requests of other types
-    interleaved to exercise batching by type."""
+    """The serving workload's shape: lognormal sizes (median 2^16, sigma 1.5)
+    clipped to [2^10, 2^24], half uniform and half duplicate-heavy u64 keys
+    with their input index as value.  Requests of 2^23 + 1 and 2^24 keys are
+    added (each takes three merge passes in its batch), and keys-only requests
+    of other types are interleaved to exercise batching by type."""
     _, sizes, dup = W.serving_requests(n_req, 1000.0, seed_arrival=seed, seed_size=seed + 1,
-                                       seed_keys=seed + 2, mu_log2=12.0, hi=1 << 18)
+                                       seed_keys=seed + 2)
+    sizes = sizes.tolist()
+    sizes[5] = (1 << 23) + 1
+    sizes[11] = 1 << 24
     reqs = []
     for i, (s, d) in enumerate(zip(sizes, dup)):
         if i % 7 == 3:
             reqs.append(("f64", W.normal_specials_f64(int(s), seed=seed * 100 + i), None))
-        elif i % 7 == 5:
+        elif i % 7 == 6:
             reqs.append(("u32", W.duplicate3_u32(int(s), seed=seed * 100 + i), None))
         else:
             reqs.append(("u64", W.request_keys(int(s), bool(d), seed=seed * 100 + i),
@@ -39,53 +48,166 @@ def _mixed_requests(n_req: int, seed: int):
     return reqs
 
 
-def _run(srv, reqs, together: bool):
+def _stage(reqs):
+    """Inputs and outputs of every request on the device, before any submit."""
     import torch
 
-    outs, tickets = [], []
+    staged = []
     for kt, k, v in reqs:
         dk = to_device(k)
-        ok = torch.empty_like(dk)
         dv = to_device(v) if v is not None else None
-        ov = torch.empty_like(dv) if v is not None else None
-        tk = srv.submit(dk, ok, dv, ov, key_type=kt)
-        outs.append((ok, ov))
-        if together:
-            tickets.append(tk)
-        else:
-            assert srv.wait(tk) == 0
-    for tk in tickets:
-        assert srv.wait(tk) == 0
-    res = []
-    for (kt, k, v), (ok, ov) in zip(reqs, outs):
-        res.append((ok.cpu().numpy().view(k.dtype),
-                    ov.cpu().numpy().view(np.uint32) if ov is not None else None))
-    return res
+        staged.append((kt, dk, torch.empty_like(dk), dv,
+                       torch.empty_like(dv) if dv is not None else None))
+    torch.cuda.synchronize()
+    return staged
+
+
+def _collect(reqs, staged):
+    return [(ok.cpu().numpy().view(k.dtype),
+             ov.cpu().numpy().view(np.uint32) if ov is not None else None)
+            for (kt, k, v), (_, _, ok, _, ov) in zip(reqs, staged)]
+
+
+def _submit_held(srv, hold):
+    """Submit each large request once the previous one has left the queue,
+    so that each occupies a worker of its own."""
+    tickets = []
+    for kt, dk, ok, dv, ov in hold:
+        tickets.append(srv.submit(dk, ok, dv, ov, key_type=kt))
+        deadline = time.time() + 10
+        while srv.stats()["queued"] and time.time() < deadline:
+            pass
+    return tickets
+
+
+def _run_mixed(srv, reqs, holders):
+    """Occupy every worker with one large request, then submit all others at
+    once: they queue while the workers are busy, so later batches take many
+    requests each."""
+    staged = _stage(reqs)
+    hold = _stage(holders)
+    tickets = _submit_held(srv, hold)
+    tickets += [srv.submit(dk, ok, dv, ov, key_type=kt) for kt, dk, ok, dv, ov in staged]
+    status = [srv.wait(t) for t in tickets]
+    assert status == [0] * len(tickets)
+    return _collect(reqs, staged), _collect(holders, hold)
+
+
+def _run_alone(srv, reqs):
+    staged = _stage(reqs)
+    for kt, dk, ok, dv, ov in staged:
+        assert srv.wait(srv.submit(dk, ok, dv, ov, key_type=kt)) == 0
+    return _collect(reqs, staged)
 
 
 def test_each_result_same_alone_and_in_the_mix():
-    import torch  # noqa: F401
-
+    import paper_2305_05245_amd as pss
     from paper_2305_05245_amd.serving import Server
 
-    reqs = _mixed_requests(48, seed=31)
-    announce("serving mix", len(reqs), "requests", sum(k.size for _, k, _ in reqs), "keys")
-    with Server(hbm_budget_bytes=3 << 28, max_streams=3) as srv:
-        mixed = _run(srv, reqs, together=True)
+    reqs = _mixed_requests(40, seed=31)
+    holders = [("u64", W.request_keys(1 << 23, False, seed=900 + i), W.index_values(1 << 23))
+               for i in range(3)]
+    total = sum(k.size for _, k, _ in reqs) + sum(k.size for _, k, _ in holders)
+    announce("serving mix", len(reqs), "requests +", len(holders), "holders", total, "keys")
+    with Server(hbm_budget_bytes=3 << 30, max_streams=3) as srv:
+        mixed, held = _run_mixed(srv, reqs, holders)
         st = srv.stats()
-        assert st["completed"] == len(reqs) and st["failed"] == 0 and st["rejected"] == 0
+        assert st["completed"] == len(reqs) + len(holders)
+        assert st["failed"] == 0 and st["rejected"] == 0
         assert 0 < st["latency_p50_ms"] <= st["latency_p99_ms"] <= st["latency_max_ms"]
-        assert st["keys_completed"] == sum(k.size for _, k, _ in reqs)
-        assert st["batches"] >= 1 and st["keys_per_s"] > 0
+        assert st["keys_completed"] == total
+        assert st["keys_per_s"] > 0
+        # continuous batching: requests that arrived while the workers were
+        # busy shared batches
+        assert st["mean_batch_requests"] > 1.0, st
+        assert st["batches"] < len(reqs) + len(holders)
+        assert st["budget_in_use"] == 0 and st["queued"] == 0
         announce("serving alone", len(reqs), "requests")
-        alone = _run(srv, reqs, together=False)
+        srv.reset_stats()
+        alone = _run_alone(srv, reqs)
+        assert srv.stats()["mean_batch_requests"] == 1.0
+    assert pss.device_check() == 0
     for i, ((kt, k, v), (mk, mv), (ak, av)) in enumerate(zip(reqs, mixed, alone)):
-        ek, eo = _stable(k)
+        ek, ev = _oracle(k, v)
         assert np.array_equal(mk.view(np.uint8), ak.view(np.uint8)), i
         assert np.array_equal(mk.view(np.uint8), ek.view(np.uint8)), i
         if v is not None:
             assert np.array_equal(mv, av), i
-            assert np.array_equal(mv, eo), i
+            assert np.array_equal(mv, ev), i
+    for i, ((kt, k, v), (hk, hv)) in enumerate(zip(holders, held)):
+        ek, ev = _oracle(k, v)
+        assert np.array_equal(hk, ek) and np.array_equal(hv, ev), i
+
+
+def test_injected_launch_fault_fails_one_batch_only():
+    """A launch armed to fail (pss_debug_inject) fails the batch it falls in:
+    every request of that batch reports PSS_ERR_HIP, every other request
+    finishes with the oracle's result, the budget in use returns to 0 and the
+    server keeps serving."""
+    import paper_2305_05245_amd as pss
+    from paper_2305_05245_amd import _lib
+    from paper_2305_05245_amd.serving import Server
+
+    reqs = [("u64", W.request_keys(n, i % 2 == 0, seed=500 + i), W.index_values(n))
+            for i, n in enumerate([3000, 70000, 1 << 17, 9000, 1 << 16, 40000, 123457, 5000,
+                                   1 << 18, 777, 60000, 1 << 15])]
+    holders = [("u64", W.request_keys(1 << 22, False, seed=950), W.index_values(1 << 22))]
+    announce("serving injected fault", len(reqs), "requests")
+    with Server(hbm_budget_bytes=1 << 30, max_streams=1) as srv:
+        staged = _stage(reqs)
+        hold = _stage(holders)
+        try:
+            # one worker: the holder's batch runs alone first (about 15
+            # launches), then the rest in one or more batches (at least 11
+            # launches more); the 20th launch fails
+            _lib.debug_inject(_lib.INJECT_LAUNCH, 19)
+            tickets = _submit_held(srv, hold)
+            tickets += [srv.submit(dk, ok, dv, ov, key_type=kt) for kt, dk, ok, dv, ov in staged]
+            status = [srv.wait(t) for t in tickets]
+        finally:
+            _lib.debug_inject(_lib.INJECT_NONE)
+        st = srv.stats()
+        failed = [i for i, s in enumerate(status) if s != 0]
+        assert failed, "the armed launch did not fail any request"
+        assert all(status[i] == _lib.ERR_HIP for i in failed)
+        assert st["failed"] == len(failed)
+        assert st["completed"] == len(tickets) - len(failed)
+        assert st["budget_in_use"] == 0 and st["queued"] == 0
+        # still serving: one more request after the fault
+        extra = _stage([reqs[0]])
+        kt, dk, ok, dv, ov = extra[0]
+        assert srv.wait(srv.submit(dk, ok, dv, ov, key_type=kt)) == 0
+        assert np.array_equal(_collect([reqs[0]], extra)[0][0], _oracle(*reqs[0][1:])[0])
+    assert pss.device_check() == 0
+    results = _collect(holders, hold) + _collect(reqs, staged)
+    for i, ((kt, k, v), (gk, gv)) in enumerate(zip(holders + reqs, results)):
+        if status[i] == 0:
+            ek, ev = _oracle(k, v)
+            assert np.array_equal(gk, ek) and np.array_equal(gv, ev), i
+
+
+def test_injected_allocation_fault_at_server_creation():
+    """An allocation armed to fail makes pss_server_create report
+    PSS_ERR_BUDGET and release what it had allocated; the next server works."""
+    import torch
+
+    from paper_2305_05245_amd import PssError, _lib
+    from paper_2305_05245_amd.serving import Server
+
+    announce("serving allocation fault")
+    try:
+        _lib.debug_inject(_lib.INJECT_ALLOC, 2)   # the third allocation fails
+        with pytest.raises(PssError) as e:
+            Server(hbm_budget_bytes=256 << 20, max_streams=2)
+        assert e.value.status == _lib.ERR_BUDGET
+    finally:
+        _lib.debug_inject(_lib.INJECT_NONE)
+    k = W.request_keys(10000, True, seed=8)
+    with Server(hbm_budget_bytes=256 << 20, max_streams=2) as srv:
+        dk = to_device(k)
+        out = torch.empty_like(dk)
+        assert srv.wait(srv.submit(dk, out, key_type="u64")) == 0
+        assert np.array_equal(out.cpu().numpy().view(np.uint64), _oracle(k, None)[0])
 
 
 def test_budget_rejects_oversize_and_serves_the_rest():
@@ -104,7 +226,7 @@ def test_budget_rejects_oversize_and_serves_the_rest():
         dk = to_device(k)
         out = torch.empty_like(dk)
         assert srv.wait(srv.submit(dk, out, key_type="u64")) == 0
-        assert np.array_equal(out.cpu().numpy().view(np.uint64), np.sort(k))
+        assert np.array_equal(out.cpu().numpy().view(np.uint64), _oracle(k, None)[0])
         st = srv.stats()
         assert st["rejected"] == 1 and st["completed"] == 1
 
@@ -135,7 +257,7 @@ def test_cancel_queued_request():
             assert srv.stats()["cancelled"] == 1
         else:
             assert r == _lib.OK
-            assert np.array_equal(out.cpu().numpy().view(np.uint64), np.sort(ks))
+            assert np.array_equal(out.cpu().numpy().view(np.uint64), _oracle(ks, None)[0])
         # a finished, uncollected request can no longer be cancelled
         t = srv.submit(dk, out, key_type="u64")
         deadline = time.time() + 30

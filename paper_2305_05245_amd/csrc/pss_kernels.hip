@@ -89,6 +89,16 @@ __device__ __forceinline__ U unmap_runtime(U x, int kt) {
 
 template <typename U> __device__ __forceinline__ constexpr U key_max() { return ~U(0); }
 
+// The same value, hidden from the optimiser (an empty asm that "changes" its
+// register).  A compare-exchange written as two selects on one comparison
+// would otherwise be rewritten as a minimum and a maximum, which the 64-bit
+// lowering computes with one comparison each; selecting between opaque
+// copies keeps one comparison for both selects.
+template <typename U> __device__ __forceinline__ U opaque(U x) {
+  asm("" : "+v"(x));
+  return x;
+}
+
 // LDS index with one pad slot after every 16 keys, so that a thread reading or
 // writing its 16 consecutive keys does not hit the same bank as its neighbours.
 __device__ __forceinline__ uint32_t pad16(uint32_t i) { return i + (i >> 4); }
@@ -147,8 +157,10 @@ __device__ __forceinline__ void register_sort(U (&k)[N], uint32_t (&v)[KV ? N : 
 #pragma unroll
     for (int c = 0; c < batcher_pairs<N>(); ++c) {
       const U x = k[net.a[c]], y = k[net.b[c]];
-      k[net.a[c]] = x < y ? x : y;
-      k[net.b[c]] = x < y ? y : x;
+      const bool lt = x < y;
+      const U ox = opaque(x), oy = opaque(y);
+      k[net.a[c]] = lt ? ox : oy;
+      k[net.b[c]] = lt ? oy : ox;
     }
   } else {
     constexpr TranspositionNet<N> net{};
@@ -259,7 +271,8 @@ __device__ __forceinline__ void merge_chunk_keys(const U *sk, uint32_t a0, uint3
     const uint32_t pn = px + (uint32_t)sizeof(U);
     const U nk = *reinterpret_cast<const U *>(base + pn);
     const bool keep = nk <= y;
-    const U nx = keep ? nk : y, ny = keep ? y : nk;
+    const U onk = opaque(nk), oy = opaque(y);
+    const U nx = keep ? onk : oy, ny = keep ? oy : onk;
     const uint32_t npx = keep ? pn : py, npy = keep ? py : pn;
     x = nx;
     y = ny;
@@ -283,8 +296,9 @@ __device__ __forceinline__ void inlane_half_cleaners(U (&k)[kTileItems]) {
       if ((i & d) == 0) {
         const U a = k[i], b = k[i + d];
         const bool sw = b < a;
-        k[i] = sw ? b : a;
-        k[i + d] = sw ? a : b;
+        const U oa = opaque(a), ob = opaque(b);
+        k[i] = sw ? ob : oa;
+        k[i + d] = sw ? oa : ob;
       }
     }
   }

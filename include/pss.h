@@ -144,6 +144,30 @@ pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys
                     void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): pss_sort
+ * with the same arguments, except that the workspace is the library's own
+ * scratch array of PSS_NOALLOC_SCRATCH_BYTES (64 MiB) on ctx's device, a
+ * fixed array that each GPU the library runs on holds until the process
+ * ends.  The call makes no device allocation (no hipMalloc or hipFree, no
+ * allocating library call); per-launch timing (pss_profile_enable) is
+ * suspended for the call, since creating timing events may allocate.
+ *   Limit: the workspace pss_workspace_bytes gives for these arguments must
+ *     fit the scratch array (keys only: about 7 million int64 or 14 million
+ *     int32 keys; with uint32 values fewer); a larger request returns
+ *     PSS_ERR_WORKSPACE and launches nothing.
+ *   Every call on one GPU shares that GPU's scratch array, which keeps the
+ *     last call's contents (no part of it needs to start at zero).  Calls
+ *     that overlap on one GPU (on different streams, or from host threads
+ *     that do not order them) race on it and give wrong results.
+ * Other arguments, ownership and errors as for pss_sort.
+ */
+#define PSS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+pss_status pss_sort_noalloc(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys_in,
+                            void *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
+                            uint64_t n, uint32_t n_blocks, uint32_t n_parts, void *stream);
+
+/*
  * Steps 1-3 of the paper's method with explicit n_B, n_P (n_blocks, n_parts
  * > 0), for inspection and parity checks.  Any output may be NULL.
  *   sorted_blocks: n keys, the concatenation of the sorted blocks (step 1).

@@ -20,6 +20,8 @@ KEY_NAMES = {"u32": U32, "i32": I32, "u64": U64, "i64": I64, "f32": F32, "f64": 
 KEY_BYTES = {U32: 4, I32: 4, U64: 8, I64: 8, F32: 4, F64: 8}
 # pss_val_t
 VAL_NONE, VAL_U32 = 0, 1
+# PSS_NOALLOC_SCRATCH_BYTES: the scratch array of pss_sort_noalloc
+NOALLOC_SCRATCH_BYTES = 64 << 20
 # pss_inject_t
 INJECT_NONE, INJECT_LAUNCH, INJECT_ALLOC = 0, 1, 2
 # pss_status
@@ -92,6 +94,7 @@ SIGNATURES = {
     "pss_psrs_splitters": (_int, [_vp, _int, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp,
                                   _sz, _vp]),
     "pss_debug_inject": (_int, [_int, _c.c_int64]),
+    "pss_sort_noalloc": (_int, [_vp, _int, _int, _vp, _vp, _vp, _vp, _u64, _u32, _u32, _vp]),
 }
 
 _lock = threading.Lock()
@@ -262,6 +265,13 @@ class Context:
         self._call("pss_sort", key, val, keys_in or None, keys_out or None,
                    vals_in or None, vals_out or None, n, n_blocks, n_parts,
                    ws or None, ws_bytes, stream or None)
+
+    def sort_noalloc(self, key: int, val: int, keys_in: int, keys_out: int, vals_in: int,
+                     vals_out: int, n: int, n_blocks: int, n_parts: int, stream: int) -> None:
+        """pss_sort_noalloc: pss_sort on the library's fixed scratch array
+        (no workspace argument, no allocation)."""
+        self._call("pss_sort_noalloc", key, val, keys_in or None, keys_out or None,
+                   vals_in or None, vals_out or None, n, n_blocks, n_parts, stream or None)
 
     def profile(self, on: bool) -> None:
         self._call("pss_profile_enable", 1 if on else 0)

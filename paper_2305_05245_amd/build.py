@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpss.so")
-SOURCES = ["pss_kernels.hip", "pss_api.hip", "pss_server.hip"]
+SOURCES = ["pss_kernels.hip", "pss_api.hip", "pss_server.hip", "pss_noalloc.hip"]
 ARCH = "gfx950"
 
 

@@ -52,8 +52,12 @@ constexpr uint64_t kMaxTableEntries = (uint64_t)1 << 28;
 // Merge passes that sort every segment of seg_len keys, starting from sorted
 // tiles of kTile keys: the number of doublings needed is split as evenly as
 // possible over passes of at most 2^kMaxFanLog2 runs each.
-std::vector<pss::RunGeom> plan_segment_passes(uint64_t n, uint64_t seg_len) {
-  std::vector<pss::RunGeom> passes;
+using PassList = pss::FixedVec<pss::RunGeom, pss::kMaxPlanPasses>;
+using KeyBufs = pss::FixedVec<void *, pss::kMaxPlanPasses + 1>;
+using ValBufs = pss::FixedVec<uint32_t *, pss::kMaxPlanPasses + 1>;
+
+PassList plan_segment_passes(uint64_t n, uint64_t seg_len) {
+  PassList passes;
   if (n == 0 || seg_len == 0) return passes;
   const uint64_t tiles = ceil_div(seg_len, pss::kTile);
   int bits = 0;
@@ -87,7 +91,7 @@ struct Plan {
   int kb = 8;
   uint64_t n = 0;
   uint64_t seg_len = 0;               // segment sorted by tile sort + passes
-  std::vector<pss::RunGeom> passes;   // merge passes inside each segment
+  PassList passes;                    // merge passes inside each segment
   pss::RunGeom top{};                 // paper mode: the cross-block merge
   // paper mode with at most kMaxSampledFan blocks of at least 2^16 keys: the
   // last block pass leaves every kSample-th key of each block, and the
@@ -405,8 +409,12 @@ pss_status run_auto_sort(pss_ctx *ctx, const Plan &p, int kt, const void *keys_i
                          const uint32_t *vals_in, void *keys_out, uint32_t *vals_out, char *w,
                          hipStream_t s) {
   const size_t P = p.passes.size();
-  std::vector<void *> kb(P + 1);
-  std::vector<uint32_t *> vb(P + 1, nullptr);
+  KeyBufs kb;
+  ValBufs vb;
+  for (size_t q = 0; q <= P; ++q) {
+    kb.push_back(nullptr);
+    vb.push_back(nullptr);
+  }
   for (size_t q = 0; q <= P; ++q) {
     const bool to_out = ((P - q) % 2) == 0;
     kb[q] = to_out ? keys_out : (void *)(w + p.off_keys0);
@@ -492,8 +500,12 @@ pss_status run_psrs(pss_ctx *ctx, const PsrsPlan &pp, int kt, const void *keys_i
                     const PsrsOut &o, bool merge, char *w, hipStream_t s) {
   const Plan &p = pp.base;
   const size_t P = p.passes.size();
-  std::vector<void *> kbuf(P + 1);
-  std::vector<uint32_t *> vbuf(P + 1, nullptr);
+  KeyBufs kbuf;
+  ValBufs vbuf;
+  for (size_t q = 0; q <= P; ++q) {
+    kbuf.push_back(nullptr);
+    vbuf.push_back(nullptr);
+  }
   for (size_t q = 0; q <= P; ++q) {
     const bool even = ((P - q) % 2) == 0;
     kbuf[q] = even ? (void *)(w + p.off_keys0) : (void *)(w + p.off_keys1);
@@ -635,6 +647,12 @@ RunGeom sample_geom(const RunGeom &g) {
 
 void set_thread_error(const char *msg) { g_thread_error = msg; }
 int ctx_device(const pss_ctx *ctx) { return ctx->device; }
+pss_status ctx_fail(const pss_ctx *ctx, pss_status s, const char *msg) { return fail(ctx, s, msg); }
+bool ctx_set_profiling(pss_ctx *ctx, bool on) {
+  const bool was = ctx->profiling;
+  ctx->profiling = on;
+  return was;
+}
 }  // namespace pss
 
 namespace pss {
@@ -679,6 +697,10 @@ pss_status pss_create(int device, pss_ctx **out) {
   if (device < 0 || device >= count) return fail(nullptr, PSS_ERR_HIP, "no such HIP device");
   e = hipSetDevice(device);
   if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  // the device address of pss_sort_noalloc's scratch array, looked up once
+  // per device with the device current; a failed lookup is reported by that
+  // entry point only
+  (void)pss::scratch_setup(device);
   pss_ctx *c = new (std::nothrow) pss_ctx;
   if (!c) return fail(nullptr, PSS_ERR_OOM, "out of host memory");
   c->device = device;
@@ -851,8 +873,12 @@ pss_status pss_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const void *keys
     if (st != PSS_OK) return st;
   } else {
     // block sort ends in workspace buffer 0; the cross-block merge writes out
-    std::vector<void *> kb(P + 1);
-    std::vector<uint32_t *> vb(P + 1, nullptr);
+    KeyBufs kb;
+    ValBufs vb;
+    for (size_t q = 0; q <= P; ++q) {
+      kb.push_back(nullptr);
+      vb.push_back(nullptr);
+    }
     for (size_t q = 0; q <= P; ++q) {
       const bool even = ((P - q) % 2) == 0;
       kb[q] = even ? (void *)(w + p.off_keys0) : (void *)(w + p.off_keys1);
@@ -1214,8 +1240,12 @@ pss_status pss_splitters(pss_ctx *ctx, pss_key_t key, const void *keys_in, uint6
   char *w = (char *)ws;
   uint32_t *table = (uint32_t *)(w + p.off_table);
   const size_t P = p.passes.size();
-  std::vector<void *> kb(P + 1);
-  std::vector<uint32_t *> vb(P + 1, nullptr);
+  KeyBufs kb;
+  ValBufs vb;
+  for (size_t q = 0; q <= P; ++q) {
+    kb.push_back(nullptr);
+    vb.push_back(nullptr);
+  }
   for (size_t q = 0; q <= P; ++q) {
     const bool even = ((P - q) % 2) == 0;
     kb[q] = even ? (void *)(w + p.off_keys0) : (void *)(w + p.off_keys1);

@@ -7,7 +7,7 @@
 #include <cstdint>
 #include <cstring>
 
-struct pss_ctx;
+#include "../../include/pss.h"
 
 namespace pss {
 
@@ -105,6 +105,32 @@ struct RunGeom {
   }
 };
 
+// A vector of at most N elements held inline: the launch plans of a sort
+// use it so that planning and launching a sort allocate no memory.
+template <typename T, int N> class FixedVec {
+ public:
+  size_t size() const { return n_; }
+  bool empty() const { return n_ == 0; }
+  // false (and nothing stored) when full
+  bool push_back(const T &v) {
+    if (n_ >= (size_t)N) return false;
+    a_[n_++] = v;
+    return true;
+  }
+  T &operator[](size_t i) { return a_[i]; }
+  const T &operator[](size_t i) const { return a_[i]; }
+  T *data() { return a_; }
+  const T *begin() const { return a_; }
+  const T *end() const { return a_ + n_; }
+
+ private:
+  T a_[N] = {};
+  size_t n_ = 0;
+};
+
+// Merge passes one plan may hold (n < 2^31 needs at most 7 at fan-in 32).
+constexpr int kMaxPlanPasses = 8;
+
 // Bits of the device error word (see read_device_error).
 constexpr uint32_t kErrCandidates = 1u;  // splitter search: candidate set overflow
 constexpr uint32_t kErrBracket = 2u;     // splitter search: target outside bracket
@@ -135,6 +161,13 @@ void set_thread_error(const char *msg);
 
 // HIP device a context is bound to.
 int ctx_device(const pss_ctx *ctx);
+// Record msg as the context's (and the calling thread's) last error.
+pss_status ctx_fail(const pss_ctx *ctx, pss_status s, const char *msg);
+// Turn a context's per-launch timing on or off; returns the previous setting.
+bool ctx_set_profiling(pss_ctx *ctx, bool on);
+// Look up, once per device and with that device current, the device address
+// of the allocation-free entry point's scratch array (pss_create calls it).
+hipError_t scratch_setup(int device);
 
 // Whether an enum argument, which a C caller may have set to any int, holds
 // one of 0..max.  Its bits are read as an int and never loaded as the C++

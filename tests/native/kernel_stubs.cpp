@@ -1,7 +1,7 @@
-// Stand-ins for the kernel launchers of pss_kernels.hip, so that the host
-// code of pss_api.hip can be linked into a host-only test program without the
-// device code.  Each reports hipErrorNotSupported; the host checks never
-// reach them.
+// Stand-ins for the kernel launchers of pss_kernels.hip (and the scratch
+// address lookup of pss_noalloc.hip), so that the host code of pss_api.hip
+// can be linked into a host-only test program without the device code.  Each
+// reports hipErrorNotSupported; the host checks never reach them.
 #include "../../paper_2305_05245_amd/csrc/pss_internal.hpp"
 
 namespace pss {
@@ -9,6 +9,7 @@ namespace {
 hipError_t none() { return hipErrorNotSupported; }
 }  // namespace
 
+hipError_t scratch_setup(int) { return none(); }
 hipError_t read_device_error(uint32_t *, bool) { return none(); }
 hipError_t read_device_error_async(uint32_t *, hipStream_t) { return none(); }
 hipError_t launch_tile_sort(int, bool, const void *, const uint32_t *, void *, uint32_t *, uint64_t,

@@ -500,7 +500,8 @@ def bench_batched(pss, torch, steps: int, warmup: int) -> dict:
     if best is None:
         best = autotune.tune(_lib.I64, _lib.VAL_NONE, total, n_segs, reps=2, store=False)
         source = "tuned now"
-    tu = _lib.Tuning(int(best["small_max_2k"]), int(best["small_max_4k"]), int(sizes.max()))
+    tu = _lib.Tuning(int(best["small_max_2k"]), int(best["small_max_4k"]), int(sizes.max()),
+                     int(best.get("fan_log2", 5)), 0)
     ws = torch.empty(_lib.segmented_workspace_bytes(_lib.I64, _lib.VAL_NONE, total, n_segs, tu),
                      dtype=torch.uint8, device="cuda")
     ctx = _context(0)

@@ -253,7 +253,7 @@ pss_status pss_sort_records(pss_ctx *ctx, pss_key_t key, const void *records_in,
  * trip, so the sequence can be captured once into a hipGraph and replayed.
  * The segments' shapes are read on the device: a planning kernel classifies
  * every segment (one small tile, or tiles of 8192 keys plus merge passes of
- * fan-in 32 with exact splitting, the paper's steps 2-4 applied per segment),
+ * fan-in 32 or 64 with exact splitting, the paper's steps 2-4 applied per segment),
  * and every later kernel finds its segment through the plan's prefix tables.
  *
  *   seg_offsets: DEVICE array of n_segs + 1 uint64, seg_offsets[0] = 0,
@@ -272,6 +272,10 @@ typedef struct {
   uint32_t small_max_2k; /* segments with <= this many keys: 2048-key tiles, 128 threads (<= 2048) */
   uint32_t small_max_4k; /* segments with <= this many keys: 4096-key tiles, 256 threads (<= 4096) */
   uint64_t max_seg_len;  /* upper bound on any segment's length; 0 = n */
+  uint32_t fan_log2;     /* runs merged per pass, as a power of two: 5 (32 runs) or 6 (64 runs,
+                            fewer passes for segments of 33-64 tiles and 1025-4096 tiles, each
+                            pass with one more merge round); 0 = 5 */
+  uint32_t reserved;     /* 0 */
 } pss_tuning;
 
 #define PSS_MAX_SEGMENTS 16777216u

@@ -186,10 +186,9 @@ def _resolve_tuning(tuning, kt, vt, n, n_segs, max_seg_len):
             from . import autotune
 
             d = autotune.cached(kt, vt, n, n_segs)
-        tu = _lib.Tuning(int(d.get("small_max_2k", 2048)) if d else 2048,
-                         int(d.get("small_max_4k", 4096)) if d else 4096, 0)
+        tu = _lib.Tuning.from_dict({k: v for k, v in (d or {}).items() if k != "max_seg_len"})
     if max_seg_len is not None and tu.max_seg_len == 0:
-        tu = _lib.Tuning(tu.small_max_2k, tu.small_max_4k, int(max_seg_len))
+        tu = _lib.Tuning(tu.small_max_2k, tu.small_max_4k, int(max_seg_len), tu.fan_log2, 0)
     return tu
 
 

@@ -186,15 +186,23 @@ def plan(key: int, val: int, n: int, n_blocks: int = 0, n_parts: int = 0) -> dic
 
 
 class Tuning(ctypes.Structure):
-    """pss_tuning: which segments use the 2048- and 4096-key tile sorts, and a
-    bound on the longest segment (bounds the merge passes launched)."""
+    """pss_tuning: which segments use the 2048- and 4096-key tile sorts, a
+    bound on the longest segment (bounds the merge passes launched), and the
+    runs merged per pass (fan_log2: 5 or 6, 0 = 5)."""
 
     _fields_ = [("small_max_2k", ctypes.c_uint32), ("small_max_4k", ctypes.c_uint32),
-                ("max_seg_len", ctypes.c_uint64)]
+                ("max_seg_len", ctypes.c_uint64), ("fan_log2", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {"small_max_2k": self.small_max_2k, "small_max_4k": self.small_max_4k,
-                "max_seg_len": self.max_seg_len}
+                "max_seg_len": self.max_seg_len, "fan_log2": self.fan_log2 or 5}
+
+    @classmethod
+    def from_dict(cls, d: dict | None, max_seg_len: int = 0) -> "Tuning":
+        d = d or {}
+        return cls(int(d.get("small_max_2k", 2048)), int(d.get("small_max_4k", 4096)),
+                   int(d.get("max_seg_len", max_seg_len)), int(d.get("fan_log2", 0)), 0)
 
 
 def segmented_workspace_bytes(key: int, val: int, n: int, n_segs: int,

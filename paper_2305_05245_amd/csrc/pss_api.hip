@@ -916,18 +916,19 @@ namespace {
 struct SegPlan {
   uint32_t max_passes = 0;
   uint32_t small0 = 2048, small1 = 4096;
+  uint32_t fan_log2 = pss::kMaxFanLog2;  // runs merged per pass, log2
   std::vector<pss::RunGeom> g, gs;  // per pass: key level and sample level
   uint64_t ns = 0;                  // bound on samples
   size_t off_keys = 0, off_vals = 0, off_plan = 0, off_samples = 0, off_skeys = 0;
   size_t off_sruns = 0, off_table = 0, off_stable = 0, off_prefix = 0, total = 0;
 };
 
-uint32_t passes_for(uint64_t L) {
+uint32_t passes_for(uint64_t L, uint32_t fan_log2) {
   if (L <= (uint64_t)pss::kTile) return 0;
   const uint64_t tiles = ceil_div(L, pss::kTile);
   uint32_t bits = 0;
   while (((uint64_t)1 << bits) < tiles) ++bits;
-  return (bits + pss::kMaxFanLog2 - 1) / pss::kMaxFanLog2;
+  return (bits + fan_log2 - 1) / fan_log2;
 }
 
 pss_status make_seg_plan(const pss_ctx *ctx, pss_key_t key, pss_val_t val, uint64_t n,
@@ -944,19 +945,23 @@ pss_status make_seg_plan(const pss_ctx *ctx, pss_key_t key, pss_val_t val, uint6
     sp->small0 = tu->small_max_2k;
     sp->small1 = tu->small_max_4k;
     if (tu->max_seg_len) max_len = std::min<uint64_t>(tu->max_seg_len, n);
+    if (tu->fan_log2 != 0 && tu->fan_log2 != 5 && tu->fan_log2 != 6)
+      return fail(ctx, PSS_ERR_INVALID, "tuning: fan_log2 must be 0, 5 or 6");
+    if (tu->fan_log2) sp->fan_log2 = tu->fan_log2;
   }
+  const uint32_t f = sp->fan_log2;
   const int kb = pss::key_bytes((int)key);
   const bool kv = val == PSS_VAL_U32;
-  sp->max_passes = passes_for(max_len);
+  sp->max_passes = passes_for(max_len, f);
   sp->ns = n >> pss::kSampleLog2;
   const uint64_t S = n_segs;
   uint64_t max_rows = 0, max_srows = 0, max_sparts = 0;
   for (uint32_t q = 1; q <= sp->max_passes; ++q) {
     pss::RunGeom g{};
     g.n = n;
-    g.run_len = (uint64_t)pss::kTile << (pss::kMaxFanLog2 * (q - 1));
-    g.fan = 1u << pss::kMaxFanLog2;
-    g.group_len = g.run_len << pss::kMaxFanLog2;
+    g.run_len = (uint64_t)pss::kTile << (f * (q - 1));
+    g.fan = 1u << f;
+    g.group_len = g.run_len << f;
     g.part_len = pss::kPart;
     g.rows_per_group = (uint32_t)(g.group_len / pss::kPart) + 1;
     const uint64_t groups = n / g.group_len + S + 1;
@@ -992,10 +997,9 @@ pss_status make_seg_plan(const pss_ctx *ctx, pss_key_t key, pss_val_t val, uint6
     sp->off_samples = take(sp->ns * (size_t)kb);
     sp->off_skeys = take(sp->ns * (size_t)kb);
     sp->off_sruns = take(sp->ns * sizeof(uint32_t));
-    sp->off_table = take(max_rows * (1u << pss::kMaxFanLog2) * sizeof(uint32_t));
-    sp->off_stable = take(max_srows * (1u << pss::kMaxFanLog2) * sizeof(uint32_t));
-    sp->off_prefix =
-        take(max_sparts * (pss::kPart / pss::kChunk) * (1u << pss::kMaxFanLog2) * sizeof(uint32_t));
+    sp->off_table = take(max_rows * (1u << f) * sizeof(uint32_t));
+    sp->off_stable = take(max_srows * (1u << f) * sizeof(uint32_t));
+    sp->off_prefix = take(max_sparts * (pss::kPart / pss::kChunk) * (1u << f) * sizeof(uint32_t));
   }
   sp->total = off;
   return PSS_OK;
@@ -1078,7 +1082,8 @@ pss_status pss_segmented_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const 
   const uint64_t sweep = 2 * n * (kbytes + (kv ? 4 : 0));
   {
     LaunchTimer t(ctx, "segment_plan", (uint64_t)n_segs * 16, s);
-    PSS_LAUNCH(pss::launch_seg_plan(seg_offsets, n_segs, n, pp, sp.small0, sp.small1, sp.max_passes, s),
+    PSS_LAUNCH(pss::launch_seg_plan(seg_offsets, n_segs, n, pp, sp.small0, sp.small1, sp.max_passes,
+                                    sp.fan_log2, s),
             "segment plan launch");
   }
   {

@@ -33,7 +33,8 @@ constexpr int kCorankThreads = 64;
 // Largest number of runs one splitter search handles (LDS-bound: the
 // candidate set of one level is below 3 * runs).
 constexpr uint32_t kMaxRuns = 2048;
-// Runs merged by one pass of the automatic plan (powers of two).
+// Runs merged by one pass of the automatic plan (powers of two); the
+// segmented mode's default (its tuning may choose 6).
 constexpr int kMaxFanLog2 = 5;
 
 // Every sorted run also leaves a regular sample: the keys at run positions
@@ -212,7 +213,7 @@ hipError_t launch_tile_sort(int kt, bool kv, const void *in, const uint32_t *vin
                             void *samples, hipStream_t s);
 hipError_t launch_seg_plan(const uint64_t *seg_off, uint32_t n_segs, uint64_t n,
                            const SegPlanPtrs &pp, uint32_t small0, uint32_t small1,
-                           uint32_t max_passes, hipStream_t s);
+                           uint32_t max_passes, uint32_t fan_log2, hipStream_t s);
 hipError_t launch_seg_tile_sorts(int kt, bool kv, const void *in, const uint32_t *vin, void *out,
                                  void *out_alt, uint32_t *vout, uint32_t *vout_alt, void *samples,
                                  const uint64_t *seg_off, const SegPlanPtrs &pp, uint32_t n_segs,

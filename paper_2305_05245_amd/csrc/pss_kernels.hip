@@ -2353,7 +2353,8 @@ __device__ void block_inclusive_scan_u64(uint64_t *a, uint32_t n, uint64_t *wsum
 __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint64_t *__restrict__ off,
                                                         uint32_t n_segs, uint64_t n,
                                                         SegPlanArrays pa, uint32_t small0,
-                                                        uint32_t small1, uint32_t max_passes) {
+                                                        uint32_t small1, uint32_t max_passes,
+                                                        uint32_t fan_log2) {
   __shared__ uint64_t wsum[17];
   __shared__ uint32_t bad;
   const uint32_t tid = threadIdx.x;
@@ -2384,7 +2385,7 @@ __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint64_t *__restri
       const uint64_t tiles = (L + kTile - 1) / kTile;
       uint32_t bits = 0;
       while (((uint64_t)1 << bits) < tiles) ++bits;
-      np = (bits + kMaxFanLog2 - 1) / kMaxFanLog2;
+      np = (bits + fan_log2 - 1) / fan_log2;
     }
     if (np > max_passes) {  // the host bound on passes was too small
       atomicOr(&bad, 2u);
@@ -2399,8 +2400,8 @@ __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint64_t *__restri
     for (uint32_t q = 1; q <= max_passes; ++q) {
       uint64_t rows = 0, parts = 0, srows = 0, sparts = 0;
       if (q <= np) {
-        const uint64_t R = (uint64_t)kTile << (kMaxFanLog2 * (q - 1));
-        const uint64_t G = R << kMaxFanLog2, Gs = G >> kSampleLog2;
+        const uint64_t R = (uint64_t)kTile << (fan_log2 * (q - 1));
+        const uint64_t G = R << fan_log2, Gs = G >> kSampleLog2;
         const uint64_t ng = (L + G - 1) / G;
         for (uint64_t gg = 0; gg < ng; ++gg) {
           const uint64_t glen = L - gg * G < G ? L - gg * G : G;
@@ -2481,7 +2482,7 @@ hipError_t launch_tile_sort(int kt, bool kv, const void *in, const uint32_t *vin
 
 hipError_t launch_seg_plan(const uint64_t *seg_off, uint32_t n_segs, uint64_t n,
                            const SegPlanPtrs &pp, uint32_t small0, uint32_t small1,
-                           uint32_t max_passes, hipStream_t s) {
+                           uint32_t max_passes, uint32_t fan_log2, hipStream_t s) {
   SegPlanArrays pa{};
   for (int c = 0; c < 3; ++c) pa.tiles[c] = pp.tiles[c];
   pa.soff = pp.soff;
@@ -2493,7 +2494,7 @@ hipError_t launch_seg_plan(const uint64_t *seg_off, uint32_t n_segs, uint64_t n,
     pa.sparts[q] = pp.sparts[q];
   }
   hipLaunchKernelGGL(seg_plan_kernel, dim3(1), dim3(1024), 0, s, seg_off, n_segs, n, pa, small0,
-                     small1, max_passes);
+                     small1, max_passes, fan_log2);
   return hipGetLastError();
 }
 

@@ -153,7 +153,7 @@ struct Worker {
 struct pss_server {
   int device = 0;
   size_t budget = 0, share = 0;
-  pss_tuning tuning{2048, 4096, 0};
+  pss_tuning tuning{2048, 4096, 0, 0, 0};
   std::unique_ptr<pss::RequestQueue> queue;
   std::vector<std::unique_ptr<Worker>> workers;
 };
@@ -281,6 +281,8 @@ pss_status pss_server_create(pss_ctx *ctx, size_t hbm_budget_bytes, uint32_t max
   if (tuning && (tuning->small_max_2k > 2048 || tuning->small_max_4k > 4096 ||
                  tuning->small_max_2k > tuning->small_max_4k))
     return server_fail(PSS_ERR_INVALID, "tuning: need small_max_2k <= small_max_4k, <= 2048, <= 4096");
+  if (tuning && tuning->fan_log2 != 0 && tuning->fan_log2 != 5 && tuning->fan_log2 != 6)
+    return server_fail(PSS_ERR_INVALID, "tuning: fan_log2 must be 0, 5 or 6");
   const size_t share = hbm_budget_bytes / max_streams / kAlign * kAlign;
   if (share < ((size_t)1 << 20))
     return server_fail(PSS_ERR_BUDGET, "budget below 1 MiB per stream");

@@ -34,8 +34,7 @@ class SegmentedGraph:
         self.offsets = torch.zeros(self.seg_cap + 1, dtype=torch.int64, device=d)
         self.offsets_host = torch.zeros(self.seg_cap + 1, dtype=torch.int64, pin_memory=True)
         t = tuning or {}
-        self.tuning = _lib.Tuning(int(t.get("small_max_2k", 2048)), int(t.get("small_max_4k", 4096)),
-                                  int(t.get("max_seg_len", 0)))
+        self.tuning = _lib.Tuning.from_dict(t)
         need = _lib.segmented_workspace_bytes(self.kt, self.vt, self.n_cap, self.seg_cap, self.tuning)
         self.ws = torch.empty(max(need, 256), dtype=torch.uint8, device=d)
         torch.cuda.synchronize(d)

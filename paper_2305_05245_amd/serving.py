@@ -28,8 +28,7 @@ class Server:
         ctx = _context(device)
         tu = tuning
         if isinstance(tuning, dict):
-            tu = _lib.Tuning(int(tuning.get("small_max_2k", 2048)),
-                             int(tuning.get("small_max_4k", 4096)), 0)
+            tu = _lib.Tuning.from_dict({k: v for k, v in tuning.items() if k != "max_seg_len"})
         h = ctypes.c_void_p()
         _lib.check(self.lib.pss_server_create(ctx.handle, int(hbm_budget_bytes), int(max_streams),
                                               ctypes.byref(tu) if tu is not None else None,

@@ -79,10 +79,16 @@ int main() {
         size_t wrec = 0;
         CHECK(pss_records_workspace_bytes(nullptr, (pss_key_t)kt, n, &wrec) == PSS_OK);
         for (uint32_t segs : {1u, 7u, 4096u}) {
-          pss_tuning tu{2048, 4096, 0};
-          size_t wseg = 0;
-          CHECK(pss_segmented_workspace_bytes(nullptr, (pss_key_t)kt, (pss_val_t)v, n, segs, &tu,
-                                              &wseg) == PSS_OK);
+          for (uint32_t f : {0u, 5u, 6u}) {
+            pss_tuning tu{2048, 4096, 0, f, 0};
+            size_t wseg = 0;
+            CHECK(pss_segmented_workspace_bytes(nullptr, (pss_key_t)kt, (pss_val_t)v, n, segs, &tu,
+                                                &wseg) == PSS_OK);
+          }
+          pss_tuning bad{2048, 4096, 0, 4, 0};
+          size_t wb = 0;
+          CHECK(pss_segmented_workspace_bytes(nullptr, (pss_key_t)kt, (pss_val_t)v, n, segs, &bad,
+                                              &wb) == PSS_ERR_INVALID);
         }
       }
     }

@@ -136,3 +136,18 @@ def test_server_structs_match_the_header():
     # pss_request: two enums, four pointers, two uint64; pss_stats: 7 uint64 + 7 double
     assert ctypes.sizeof(_lib.Request) == 8 + 4 * 8 + 2 * 8
     assert ctypes.sizeof(_lib.Stats) == 16 * 8
+
+
+def test_tuning_struct_and_fan_choice(lib):
+    # pss_tuning: two uint32, one uint64, two uint32
+    assert ctypes.sizeof(_lib.Tuning) == 24
+    n, segs = 1 << 22, 16
+    w5 = _lib.segmented_workspace_bytes(_lib.I64, 0, n, segs, _lib.Tuning(2048, 4096, 1 << 19, 5, 0))
+    w6 = _lib.segmented_workspace_bytes(_lib.I64, 0, n, segs, _lib.Tuning(2048, 4096, 1 << 19, 6, 0))
+    w0 = _lib.segmented_workspace_bytes(_lib.I64, 0, n, segs, _lib.Tuning(2048, 4096, 1 << 19, 0, 0))
+    assert w0 == w5 and w6 > 0
+    with pytest.raises(_lib.PssError) as e:
+        _lib.segmented_workspace_bytes(_lib.I64, 0, n, segs, _lib.Tuning(2048, 4096, 0, 4, 0))
+    assert e.value.status == _lib.ERR_INVALID
+    d = _lib.Tuning.from_dict({"small_max_2k": 512, "fan_log2": 6}).as_dict()
+    assert d["small_max_2k"] == 512 and d["small_max_4k"] == 4096 and d["fan_log2"] == 6

@@ -116,8 +116,10 @@ def test_segmented_key_value_stable(dtype):
 @pytest.mark.parametrize("tuning", [{"small_max_2k": 0, "small_max_4k": 0},
                                     {"small_max_2k": 512, "small_max_4k": 2048},
                                     {"small_max_2k": 2048, "small_max_4k": 4096},
-                                    {"small_max_2k": 1024, "small_max_4k": 4096}],
-                         ids=["all8k", "512-2k", "2k-4k", "1k-4k"])
+                                    {"small_max_2k": 1024, "small_max_4k": 4096},
+                                    {"small_max_2k": 2048, "small_max_4k": 4096, "fan_log2": 6},
+                                    {"small_max_2k": 0, "small_max_4k": 0, "fan_log2": 6}],
+                         ids=["all8k", "512-2k", "2k-4k", "1k-4k", "2k-4k-fan64", "all8k-fan64"])
 def test_segmented_every_tuning_same_output(tuning):
     offs = mixed_offsets(3)
     keys = keys_for(np.int64, int(offs[-1]), 11)
@@ -176,13 +178,16 @@ def test_segmented_full_batch_4096_segments():
             assert same(got[lo:hi], r.keys), i
 
 
+@pytest.mark.parametrize("fan", [5, 6], ids=["fan32", "fan64"])
 @pytest.mark.parametrize("kv", [False, True], ids=["keys", "key-value"])
-def test_segmented_three_merge_passes(kv):
-    """Segments above 2^23 keys take three merge passes (2^11+ tiles of 8192
-    keys) with the segment's data ending in the output or the workspace by
-    the parity of its own pass count: segments of 2^23 + 1 and 2^24 keys (three
-    passes), 2^23 (two), 2^20 + 3 (two) and short ones (none or one), mixed,
-    against the oracle segment by segment."""
+def test_segmented_three_merge_passes(kv, fan):
+    """Segments above 2^23 keys take three merge passes of 32 runs (2^11+
+    tiles of 8192 keys) with the segment's data ending in the output or the
+    workspace by the parity of its own pass count: segments of 2^23 + 1 and
+    2^24 keys (three passes), 2^23 (two), 2^20 + 3 (two) and short ones (none
+    or one), mixed, against the oracle segment by segment.  With 64 runs per
+    pass the same segments take two passes (2^24: 2048 tiles = 64 x 32) and
+    2^20 + 3 one pass fewer, so the parities differ."""
     sizes = np.array([1000, (1 << 23) + 1, 5, (1 << 20) + 3, 1 << 24, 8193, 1 << 23, 0, 77],
                      dtype=np.int64)
     offs = np.zeros(sizes.size + 1, dtype=np.int64)
@@ -190,8 +195,9 @@ def test_segmented_three_merge_passes(kv):
     keys = np.concatenate([W.request_keys(int(s), i % 2 == 1, seed=40 + i)
                            for i, s in enumerate(sizes)]).view(np.uint64)
     vals = np.arange(keys.size, dtype=np.uint32) if kv else None
-    announce("segmented-3-pass", "kv" if kv else "keys", int(offs[-1]))
-    gk, gv = gpu_segmented(keys, offs, vals)
+    announce("segmented-3-pass", "kv" if kv else "keys", "fan", 1 << fan, int(offs[-1]))
+    gk, gv = gpu_segmented(keys, offs, vals, tuning={"small_max_2k": 2048, "small_max_4k": 4096,
+                                                     "fan_log2": fan})
     ek, ev = oracle_segmented(keys, offs, vals)
     assert same(gk, ek)
     if kv:

@@ -50,22 +50,24 @@ uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 constexpr uint64_t kMaxTableEntries = (uint64_t)1 << 28;
 
 // Merge passes that sort every segment of seg_len keys, starting from sorted
-// tiles of kTile keys: the number of doublings needed is split as evenly as
-// possible over passes of at most 2^kMaxFanLog2 runs each.
+// tiles of `tile` keys: the number of doublings needed is split as evenly as
+// possible over passes of at most 2^max_fan_log2 runs each, merged in
+// partitions of `part` keys.
 using PassList = pss::FixedVec<pss::RunGeom, pss::kMaxPlanPasses>;
 using KeyBufs = pss::FixedVec<void *, pss::kMaxPlanPasses + 1>;
 using ValBufs = pss::FixedVec<uint32_t *, pss::kMaxPlanPasses + 1>;
 
-PassList plan_segment_passes(uint64_t n, uint64_t seg_len) {
+PassList plan_segment_passes(uint64_t n, uint64_t seg_len, uint32_t tile, uint32_t part,
+                             int max_fan_log2) {
   PassList passes;
   if (n == 0 || seg_len == 0) return passes;
-  const uint64_t tiles = ceil_div(seg_len, pss::kTile);
+  const uint64_t tiles = ceil_div(seg_len, tile);
   int bits = 0;
   while (((uint64_t)1 << bits) < tiles) ++bits;
   if (bits == 0) return passes;
-  const int npass = (bits + pss::kMaxFanLog2 - 1) / pss::kMaxFanLog2;
+  const int npass = (bits + max_fan_log2 - 1) / max_fan_log2;
   const uint64_t nseg = ceil_div(n, seg_len);
-  uint64_t run = pss::kTile;
+  uint64_t run = tile;
   for (int q = 0; q < npass; ++q) {
     const int b = bits / npass + (q < bits % npass ? 1 : 0);
     pss::RunGeom g{};
@@ -76,7 +78,7 @@ PassList plan_segment_passes(uint64_t n, uint64_t seg_len) {
     g.group_len = std::min<uint64_t>((uint64_t)g.fan * run, seg_len);
     g.groups_per_seg = ceil_div(seg_len, g.group_len);
     g.n_groups = nseg * g.groups_per_seg;
-    g.part_len = pss::kPart;
+    g.part_len = part;
     g.rows_per_group = (uint32_t)ceil_div(g.group_len, g.part_len) + 1;
     g.paper = 0;
     passes.push_back(g);
@@ -90,6 +92,8 @@ struct Plan {
   bool kv = false;
   int kb = 8;
   uint64_t n = 0;
+  uint32_t tile = pss::kTile;         // keys per tile of the tile sort
+  uint32_t part = pss::kPart;         // keys per partition of the segment passes
   uint64_t seg_len = 0;               // segment sorted by tile sort + passes
   PassList passes;                    // merge passes inside each segment
   pss::RunGeom top{};                 // paper mode: the cross-block merge
@@ -114,13 +118,16 @@ pss_status make_plan(pss_key_t key, pss_val_t val, uint64_t n, uint32_t n_blocks
   p->kb = pss::key_bytes((int)key);
   p->n = n;
   p->paper = n_blocks > 0;
+  p->tile = p->kv ? pss::kTileKV : pss::kTile;
+  p->part = p->kv ? pss::kPartKV : pss::kPart;
+  const int max_fan_log2 = p->kv ? pss::kMaxFanLog2KV : pss::kMaxFanLog2;
   if (!p->paper) {
     p->seg_len = n;
-    p->passes = plan_segment_passes(n, n);
+    p->passes = plan_segment_passes(n, n, p->tile, p->part, max_fan_log2);
   } else {
     const uint64_t L = n ? ceil_div(n, n_blocks) : 0;
     p->seg_len = L;
-    p->passes = plan_segment_passes(n, L);
+    p->passes = plan_segment_passes(n, L, p->tile, p->part, max_fan_log2);
     pss::RunGeom &t = p->top;
     t.n = n;
     t.seg_len = n;
@@ -320,7 +327,7 @@ pss_status run_segment_sort(pss_ctx *ctx, const Plan &p, int kt, const void *key
   {
     LaunchTimer t(ctx, "tile_sort", sweep, s);
     PSS_LAUNCH(pss::launch_tile_sort(kt, p.kv, keys_in, vals_in, kbuf[0], vbuf[0], p.n, p.seg_len,
-                                  final_last && P == 0, samples, s),
+                                  p.tile, final_last && P == 0, samples, s),
             "tile sort launch");
   }
   for (size_t q = 1; q <= P; ++q) {
@@ -831,7 +838,7 @@ pss_status pss_plan_describe(pss_key_t key, pss_val_t val, uint64_t n, uint32_t 
   make_plan(key, val, n, n_blocks, n_parts, &p, &err);
   std::string j = "{\"mode\": \"";
   j += p.paper ? "paper" : "auto";
-  j += "\", \"tile\": " + std::to_string(pss::kTile) + ", \"part\": " + std::to_string(pss::kPart);
+  j += "\", \"tile\": " + std::to_string(p.tile) + ", \"part\": " + std::to_string(p.part);
   std::string fans;
   for (size_t i = 0; i < p.passes.size(); ++i)
     fans += (i ? ", " : "") + std::to_string(p.passes[i].fan);

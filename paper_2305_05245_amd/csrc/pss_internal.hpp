@@ -28,6 +28,17 @@ constexpr int kRoundItems = 17;
 // LDS (at least kRoundItems), so their merge steps need no bound checks.
 constexpr uint32_t kGap = kRoundItems + 1;
 
+// Key-value sorts of the automatic plan hold 12 bytes a key in LDS.  Tiles of
+// 8192 keys would leave one workgroup per CU, so they sort tiles of 4096 keys
+// (256 threads; three workgroups per CU) and merge partitions of 4096 keys in
+// chunks of 9 outputs per thread (two 1024-thread workgroups per CU), with up
+// to 64 runs per pass so that 2^28 keys still take three passes.
+constexpr int kTileKVThreads = 256;
+constexpr int kTileKV = kTileKVThreads * kTileItems;  // 4096 keys
+constexpr int kPartKV = 4096;
+constexpr int kRoundItemsKV = 9;
+constexpr int kMaxFanLog2KV = 6;
+
 // Step 2 splitter search: one 64-lane workgroup per splitter.
 constexpr int kCorankThreads = 64;
 // Largest number of runs one splitter search handles (LDS-bound: the
@@ -208,9 +219,10 @@ struct MergeAlt {
 };
 
 // samples: optional output, every kSample-th key of each sorted tile.
+// tile: kTile, or kTileKV (key-value sorts only).
 hipError_t launch_tile_sort(int kt, bool kv, const void *in, const uint32_t *vin, void *out,
-                            uint32_t *vout, uint64_t n, uint64_t seg_len, int final_pass,
-                            void *samples, hipStream_t s);
+                            uint32_t *vout, uint64_t n, uint64_t seg_len, uint32_t tile,
+                            int final_pass, void *samples, hipStream_t s);
 hipError_t launch_seg_plan(const uint64_t *seg_off, uint32_t n_segs, uint64_t n,
                            const SegPlanPtrs &pp, uint32_t small0, uint32_t small1,
                            uint32_t max_passes, uint32_t fan_log2, hipStream_t s);

@@ -1619,27 +1619,32 @@ template <typename U> struct MergeBufs {
   uint32_t *vdst, *vdst_alt;
 };
 
-template <int KT, int VMODE, uint32_t MAXF, uint32_t NT = kMergeThreads>
-__global__ __launch_bounds__(NT, (VMODE == 0 && NT > kMergeThreads) ? 2 : 1) void merge_kernel(
+template <int KT, int VMODE, uint32_t MAXF, uint32_t NT = kMergeThreads, uint32_t PART = kPart>
+__global__ __launch_bounds__(NT, (VMODE != 2 && NT > kMergeThreads && (VMODE == 0 || PART < kPart)) ? 2 : 1)
+void merge_kernel(
     MergeBufs<typename Key<KT>::U> bufs, RunGeom g, const uint32_t *__restrict__ table,
     const uint64_t *__restrict__ part_off, int final_pass,
     typename Key<KT>::U *__restrict__ samples, uint32_t *__restrict__ prefix) {
   using U = typename Key<KT>::U;
   constexpr bool KV = VMODE != 0;
-  // NT threads, ITEMS keys each; a merge round gives each thread a chunk of
-  // CI outputs (odd, and small enough that a round's chunks fit in NT).  With
-  // 1024 threads, chunks of ITEMS + 1 = 9 would keep more threads busy, but
-  // the 17-key chunks measured faster (fewer chunk boundaries to search).
-  constexpr int ITEMS = kPart / NT;
-  constexpr int CI = kRoundItems;
-  constexpr int LP = kPart / NT;  // positions each thread labels
-  static_assert(NT * ITEMS == kPart && CI % 2 == 1 && LP % 4 == 0, "merge geometry");
+  // NT threads, ITEMS keys each, partitions of at most PART keys; a merge
+  // round gives each thread a chunk of CI outputs (odd, and small enough that
+  // a round's chunks fit in NT).  On 8192-key partitions with 1024 threads,
+  // chunks of ITEMS + 1 = 9 would keep more threads busy, but the 17-key
+  // chunks measured faster (fewer chunk boundaries to search).  Key-value
+  // merges of 4096-key partitions take chunks of 9: their registers then
+  // allow two 1024-thread workgroups per CU.
+  constexpr int ITEMS = PART / NT;
+  constexpr int CI = (VMODE == 1 && PART < kPart) ? kRoundItemsKV : kRoundItems;
+  constexpr int LP = PART / NT;  // positions each thread labels
+  static_assert(NT * ITEMS == PART && CI % 2 == 1 && LP % 4 == 0, "merge geometry");
+  static_assert(PART == kPart || (VMODE == 1 && MAXF <= 64), "short partitions: key-value only");
   // Keys-only merges of at most 32 runs leave kGap slots holding the largest
   // key after every segment in LDS (see merge_chunk_keys); others use the
   // flat layout.  Both add the slack a merge chunk may read past the end.
   constexpr bool GAPS = VMODE == 0 && MAXF <= 32;
   constexpr uint32_t G = GAPS ? kGap : 0;
-  constexpr uint32_t P = kPart + MAXF * G + 2 * kRoundItems + 2;
+  constexpr uint32_t P = PART + MAXF * G + 2 * kRoundItems + 2;
   __shared__ U sk[P];
   __shared__ uint32_t sv[KV ? P : 1];
   __shared__ uint32_t soff[MAXF + 1];
@@ -1648,7 +1653,7 @@ __global__ __launch_bounds__(NT, (VMODE == 0 && NT > kMergeThreads) ? 2 : 1) voi
   __shared__ uint64_t ssrc[MAXF];
   // segment of each position, one byte each (up to 256 segments)
   constexpr bool LABELS = MAXF <= 256;
-  __shared__ uint32_t sseg[LABELS ? kPart / 4 : 1];
+  __shared__ uint32_t sseg[LABELS ? PART / 4 : 1];
   __shared__ uint32_t wsum[NT / 64 + 1];
   // per-run counts of a block of chunks (all chunks of a partition when
   // the fan is at most 64)
@@ -1688,7 +1693,7 @@ __global__ __launch_bounds__(NT, (VMODE == 0 && NT > kMergeThreads) ? 2 : 1) voi
         const uint32_t len = run_length(pi.group_len, R, tid);
         const bool ok = lo <= hi && hi <= len;
         if (!ok) report(kErrSplitRow);
-        c = ok ? hi - lo : (uint32_t)kPart + 1;  // forces the size check below to fail
+        c = ok ? hi - lo : PART + 1;  // forces the size check below to fail
         ssrc[tid] = pi.group_start + (uint64_t)tid * R + lo;
       }
       uint32_t x = c;
@@ -1709,7 +1714,7 @@ __global__ __launch_bounds__(NT, (VMODE == 0 && NT > kMergeThreads) ? 2 : 1) voi
       const uint32_t len = run_length(pi.group_len, R, b);
       const bool ok = lo <= hi && hi <= len;
       if (!ok) report(kErrSplitRow);
-      soff[b] = ok ? hi - lo : (uint32_t)kPart + 1;  // forces the size check below to fail
+      soff[b] = ok ? hi - lo : PART + 1;  // forces the size check below to fail
       ssrc[b] = pi.group_start + (uint64_t)b * R + lo;
     }
     __syncthreads();
@@ -1838,13 +1843,13 @@ __global__ __launch_bounds__(NT, (VMODE == 0 && NT > kMergeThreads) ? 2 : 1) voi
   if constexpr (MAXF <= 64) {
     // Each pair's output is cut into chunks of CI that never cross into the
     // next pair; a chunk prefix over pairs maps threads to chunks.  With at
-    // most 32 pairs, M <= kPart keys fit in NT chunks.
+    // most 32 pairs, M <= PART keys fit in NT chunks.
     uint32_t round = 0;
     for (uint32_t w = 1; w < F; w <<= 1, ++round) {
       const uint32_t npairs = (F + 2 * w - 1) / (2 * w);
       const uint32_t *cp = cpre + round * 33;
       const uint32_t nchunks = cp[npairs];
-      if (nchunks > NT && tid == 0) report(kErrPartSize);  // cannot happen for M <= kPart
+      if (nchunks > NT && tid == 0) report(kErrPartSize);  // cannot happen for M <= PART
       U rk[CI];
       uint32_t rv[KV ? CI : 1];
       uint32_t start = 0, count = 0, gap_at = 0;
@@ -2458,10 +2463,11 @@ hipError_t go_tile(const void *in, const uint32_t *vin, const TileArgs<typename 
 }  // namespace
 
 hipError_t launch_tile_sort(int kt, bool kv, const void *in, const uint32_t *vin, void *out,
-                            uint32_t *vout, uint64_t n, uint64_t seg_len, int final_pass,
-                            void *samples, hipStream_t s) {
+                            uint32_t *vout, uint64_t n, uint64_t seg_len, uint32_t tile,
+                            int final_pass, void *samples, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const uint64_t tps = (seg_len + kTile - 1) / kTile;
+  if (tile != (uint32_t)kTile && !(kv && tile == (uint32_t)kTileKV)) return hipErrorInvalidValue;
+  const uint64_t tps = (seg_len + tile - 1) / tile;
   const uint64_t nseg = (n + seg_len - 1) / seg_len;
   const uint64_t grid = nseg * tps;
   return dispatch_kt(kt, [&](auto ktc) {
@@ -2475,6 +2481,7 @@ hipError_t launch_tile_sort(int kt, bool kv, const void *in, const uint32_t *vin
     ta.out = ta.out_alt = (U *)out;
     ta.vout = ta.vout_alt = vout;
     ta.samples = (U *)samples;
+    if (kv && tile == (uint32_t)kTileKV) return go_tile<KT, true, kTileKVThreads>(in, vin, ta, grid, s);
     return kv ? go_tile<KT, true, kTileThreads>(in, vin, ta, grid, s)
               : go_tile<KT, false, kTileThreads>(in, vin, ta, grid, s);
   });
@@ -2663,6 +2670,15 @@ hipError_t launch_merge(int kt, int vmode, const void *src, const uint32_t *vsrc
       return hipGetLastError();
     };
     const bool kv = vmode == 1;
+    if (g.part_len != (uint32_t)kPart) {
+      // key-value passes of the automatic plan: 4096-key partitions
+      if (!kv || g.part_len != (uint32_t)kPartKV || g.fan > 64 || g.seg.off || g.paper)
+        return hipErrorInvalidValue;
+      constexpr uint32_t NT = 2 * kMergeThreads;
+      hipLaunchKernelGGL((merge_kernel<KT, 1, 64, NT, kPartKV>), dim3((uint32_t)parts), dim3(NT), 0,
+                         s, b, g, table, part_offsets, final_pass, (U *)samples, (uint32_t *)nullptr);
+      return hipGetLastError();
+    }
     if (!kv && g.fan <= 32) {
       constexpr uint32_t NT = 2 * kMergeThreads;
       hipLaunchKernelGGL((merge_kernel<KT, 0, 32, NT>), dim3((uint32_t)parts), dim3(NT), 0, s,

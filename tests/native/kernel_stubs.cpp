@@ -13,7 +13,7 @@ hipError_t scratch_setup(int) { return none(); }
 hipError_t read_device_error(uint32_t *, bool) { return none(); }
 hipError_t read_device_error_async(uint32_t *, hipStream_t) { return none(); }
 hipError_t launch_tile_sort(int, bool, const void *, const uint32_t *, void *, uint32_t *, uint64_t,
-                            uint64_t, int, void *, hipStream_t) { return none(); }
+                            uint64_t, uint32_t, int, void *, hipStream_t) { return none(); }
 hipError_t launch_seg_plan(const uint64_t *, uint32_t, uint64_t, const SegPlanPtrs &, uint32_t,
                            uint32_t, uint32_t, uint32_t, hipStream_t) { return none(); }
 hipError_t launch_seg_tile_sorts(int, bool, const void *, const uint32_t *, void *, void *,

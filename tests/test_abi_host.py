@@ -106,6 +106,21 @@ def test_auto_plan(lib, n, passes):
     assert p["hbm_passes"] == 1 + len(p["passes"])
 
 
+@pytest.mark.parametrize("n,passes", [
+    (4096, []), (4097, [2]), (1 << 20, [16, 16]), (1 << 22, [32, 32]),
+    (1 << 28, [64, 32, 32]), (1 << 27, [32, 32, 32]),
+])
+def test_auto_plan_key_value(lib, n, passes):
+    """Key-value sorts: 4096-key tiles and partitions, up to 64 runs a pass."""
+    p = _lib.plan(_lib.U64, _lib.VAL_U32, n)
+    assert p["mode"] == "auto" and p["tile"] == 4096 and p["part"] == 4096
+    assert p["passes"] == passes
+    prod = 1
+    for f in p["passes"]:
+        prod *= f
+    assert prod * p["tile"] >= n and max(p["passes"] or [1]) <= 64
+
+
 def test_paper_plan(lib):
     p = _lib.plan(_lib.I32, 0, 1 << 20, 64, 64)
     assert p["mode"] == "paper" and p["n_blocks"] == 64 and p["n_parts"] == 64

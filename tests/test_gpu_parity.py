@@ -110,6 +110,21 @@ def test_auto_key_value_stable(dtype, kind):
         assert same_bits(gk, ek) and np.array_equal(gv, ev), (kind, n)
 
 
+def test_key_value_fan64_passes():
+    """Key-value sorts take 4096-key tiles, 4096-key partitions and up to 64
+    runs a pass: 2^18 keys (64 tiles, one pass of 64 runs), 2^18 + 1 (two
+    passes), 2^24 (two passes of 64), uniform and three-valued keys, against
+    the oracle (keys and the stable values)."""
+    for n in (1 << 18, (1 << 18) + 1, 1 << 24):
+        for kind in ("uniform", "dup"):
+            keys = seeded_keys(np.uint64, n, 41, kind)
+            vals = np.arange(n, dtype=np.uint32)
+            announce("auto-kv-fan64", kind, n)
+            gk, gv = gpu_sort(keys, vals)
+            ek, ev = oracle_sort(keys, vals)
+            assert same_bits(gk, ek) and np.array_equal(gv, ev), (kind, n)
+
+
 def test_medium_sizes_three_passes():
     # 2^24 keys: 2048 tiles, three merge passes
     keys = W.uniform_i64(1 << 24, seed=2)
@@ -237,6 +252,22 @@ def test_full_size_int64_2p28(dist):
 @pytest.mark.parametrize("dist", list(C3))
 def test_full_size_float64_2p27(dist):
     check_full(dist, C3[dist](1 << 27))
+
+
+@pytest.mark.parametrize("dist", ["uniform", "mod1000"])
+def test_full_size_key_value_2p28(dist):
+    """The key-value workload at full size: 2^28 int64 keys with the values
+    0..N-1 (passes of 64, 32 and 32 runs).  A stable sort is unique: the
+    values must equal numpy's stable argsort of the keys, and the keys the
+    input in that order."""
+    keys = C2[dist](1 << 28)
+    vals = np.arange(keys.size, dtype=np.uint32)
+    announce("full-kv", dist, keys.size)
+    gk, gv = gpu_sort(keys, vals)
+    perm = np.argsort(keys, kind="stable")
+    assert np.array_equal(gv, perm.astype(np.uint32)), "values differ from the stable order"
+    del perm
+    assert np.array_equal(gk, keys[gv]), "keys differ from the input in the values' order"
 
 
 @pytest.mark.parametrize("dist", list(C2))

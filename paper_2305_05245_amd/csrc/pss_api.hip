@@ -924,15 +924,18 @@ struct SegPlan {
   uint32_t max_passes = 0;
   uint32_t small0 = 2048, small1 = 4096;
   uint32_t fan_log2 = pss::kMaxFanLog2;  // runs merged per pass, log2
+  // keys per tile of segments with merge passes, and per merge partition
+  // (key-value batches: 4096, as in the automatic plan)
+  uint32_t tile = pss::kTile, part = pss::kPart;
   std::vector<pss::RunGeom> g, gs;  // per pass: key level and sample level
   uint64_t ns = 0;                  // bound on samples
   size_t off_keys = 0, off_vals = 0, off_plan = 0, off_samples = 0, off_skeys = 0;
   size_t off_sruns = 0, off_table = 0, off_stable = 0, off_prefix = 0, total = 0;
 };
 
-uint32_t passes_for(uint64_t L, uint32_t fan_log2) {
-  if (L <= (uint64_t)pss::kTile) return 0;
-  const uint64_t tiles = ceil_div(L, pss::kTile);
+uint32_t passes_for(uint64_t L, uint32_t fan_log2, uint32_t tile) {
+  if (L <= (uint64_t)tile) return 0;
+  const uint64_t tiles = ceil_div(L, tile);
   uint32_t bits = 0;
   while (((uint64_t)1 << bits) < tiles) ++bits;
   return (bits + fan_log2 - 1) / fan_log2;
@@ -959,29 +962,34 @@ pss_status make_seg_plan(const pss_ctx *ctx, pss_key_t key, pss_val_t val, uint6
   const uint32_t f = sp->fan_log2;
   const int kb = pss::key_bytes((int)key);
   const bool kv = val == PSS_VAL_U32;
-  sp->max_passes = passes_for(max_len, f);
+  sp->tile = kv ? pss::kTileKV : pss::kTile;
+  sp->part = kv ? pss::kPartKV : pss::kPart;
+  sp->max_passes = passes_for(max_len, f, sp->tile);
   sp->ns = n >> pss::kSampleLog2;
   const uint64_t S = n_segs;
   uint64_t max_rows = 0, max_srows = 0, max_sparts = 0;
   for (uint32_t q = 1; q <= sp->max_passes; ++q) {
     pss::RunGeom g{};
     g.n = n;
-    g.run_len = (uint64_t)pss::kTile << (f * (q - 1));
+    g.run_len = (uint64_t)sp->tile << (f * (q - 1));
     g.fan = 1u << f;
     g.group_len = g.run_len << f;
-    g.part_len = pss::kPart;
-    g.rows_per_group = (uint32_t)(g.group_len / pss::kPart) + 1;
+    g.part_len = sp->part;
+    g.rows_per_group = (uint32_t)ceil_div(g.group_len, sp->part) + 1;
     const uint64_t groups = n / g.group_len + S + 1;
-    g.part_bound = n / pss::kPart + groups + 1;
+    g.part_bound = n / sp->part + groups + 1;
     g.row_bound = g.part_bound + groups + 1;
     g.seg_len = g.group_len;
     g.groups_per_seg = 1;
     g.n_groups = groups;
     pss::RunGeom gs = g;
+    gs.part_len = pss::kPart;  // sample merges keep 8192-key partitions
     gs.n = sp->ns;
     gs.run_len = g.run_len >> pss::kSampleLog2;
     gs.group_len = g.group_len >> pss::kSampleLog2;
-    gs.rows_per_group = (uint32_t)(gs.group_len / pss::kPart) + 1;
+    // as the planning kernel counts them: a group of 32 runs of 4096 keys
+    // leaves 4096 samples, one (short) sample partition
+    gs.rows_per_group = (uint32_t)ceil_div(gs.group_len, pss::kPart) + 1;
     gs.part_bound = sp->ns / pss::kPart + groups + 1;
     gs.row_bound = gs.part_bound + groups + 1;
     max_rows = std::max(max_rows, g.row_bound);
@@ -1090,13 +1098,13 @@ pss_status pss_segmented_sort(pss_ctx *ctx, pss_key_t key, pss_val_t val, const 
   {
     LaunchTimer t(ctx, "segment_plan", (uint64_t)n_segs * 16, s);
     PSS_LAUNCH(pss::launch_seg_plan(seg_offsets, n_segs, n, pp, sp.small0, sp.small1, sp.max_passes,
-                                    sp.fan_log2, s),
+                                    sp.fan_log2, sp.tile, sp.part, s),
             "segment plan launch");
   }
   {
     LaunchTimer t(ctx, "tile_sort", sweep, s);
     PSS_LAUNCH(pss::launch_seg_tile_sorts(kt, kv, keys_in, vals_in, keys_out, kws, vals_out, vws,
-                                       samples, seg_offsets, pp, n_segs, n, s),
+                                       samples, seg_offsets, pp, n_segs, n, sp.tile, s),
             "tile sort launch");
   }
   for (uint32_t q = 1; q <= sp.max_passes; ++q) {

@@ -225,11 +225,12 @@ hipError_t launch_tile_sort(int kt, bool kv, const void *in, const uint32_t *vin
                             int final_pass, void *samples, hipStream_t s);
 hipError_t launch_seg_plan(const uint64_t *seg_off, uint32_t n_segs, uint64_t n,
                            const SegPlanPtrs &pp, uint32_t small0, uint32_t small1,
-                           uint32_t max_passes, uint32_t fan_log2, hipStream_t s);
+                           uint32_t max_passes, uint32_t fan_log2, uint32_t tile, uint32_t part,
+                           hipStream_t s);
 hipError_t launch_seg_tile_sorts(int kt, bool kv, const void *in, const uint32_t *vin, void *out,
                                  void *out_alt, uint32_t *vout, uint32_t *vout_alt, void *samples,
                                  const uint64_t *seg_off, const SegPlanPtrs &pp, uint32_t n_segs,
-                                 uint64_t n, hipStream_t s);
+                                 uint64_t n, uint32_t tile, hipStream_t s);
 // src_alt: segmented mode's second input buffer (nullptr = same as src).
 hipError_t launch_corank(int kt, const void *src, const RunGeom &g, uint32_t *table,
                          void *pivots, uint64_t *counts, hipStream_t s,

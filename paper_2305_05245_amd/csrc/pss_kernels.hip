@@ -2359,7 +2359,8 @@ __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint64_t *__restri
                                                         uint32_t n_segs, uint64_t n,
                                                         SegPlanArrays pa, uint32_t small0,
                                                         uint32_t small1, uint32_t max_passes,
-                                                        uint32_t fan_log2) {
+                                                        uint32_t fan_log2, uint32_t tile,
+                                                        uint32_t part) {
   __shared__ uint64_t wsum[17];
   __shared__ uint32_t bad;
   const uint32_t tid = threadIdx.x;
@@ -2386,8 +2387,8 @@ __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint64_t *__restri
     const uint64_t L = ok ? off[s + 1] - off[s] : 0;
     int cls = L == 0 ? -1 : (L <= small0 ? 0 : (L <= small1 ? 1 : 2));
     uint32_t np = 0;
-    if (cls == 2 && L > (uint64_t)kTile) {
-      const uint64_t tiles = (L + kTile - 1) / kTile;
+    if (cls == 2 && L > (uint64_t)tile) {
+      const uint64_t tiles = (L + tile - 1) / tile;
       uint32_t bits = 0;
       while (((uint64_t)1 << bits) < tiles) ++bits;
       np = (bits + fan_log2 - 1) / fan_log2;
@@ -2398,21 +2399,21 @@ __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint64_t *__restri
       cls = -1;
     }
     for (int c = 0; c < 3; ++c)
-      pa.tiles[c][s + 1] = c == cls ? (c == 2 ? (L + kTile - 1) / kTile : 1) : 0;
+      pa.tiles[c][s + 1] = c == cls ? (c == 2 ? (L + tile - 1) / tile : 1) : 0;
     pa.npass[s] = np;
     pa.soff[s + 1] = np ? (L >> kSampleLog2) : 0;
     const uint64_t Ls = L >> kSampleLog2;
     for (uint32_t q = 1; q <= max_passes; ++q) {
       uint64_t rows = 0, parts = 0, srows = 0, sparts = 0;
       if (q <= np) {
-        const uint64_t R = (uint64_t)kTile << (fan_log2 * (q - 1));
+        const uint64_t R = (uint64_t)tile << (fan_log2 * (q - 1));
         const uint64_t G = R << fan_log2, Gs = G >> kSampleLog2;
         const uint64_t ng = (L + G - 1) / G;
         for (uint64_t gg = 0; gg < ng; ++gg) {
           const uint64_t glen = L - gg * G < G ? L - gg * G : G;
           const uint64_t gs = gg * Gs < Ls ? (Ls - gg * Gs < Gs ? Ls - gg * Gs : Gs) : 0;
-          parts += (glen + kPart - 1) / kPart;
-          rows += (glen + kPart - 1) / kPart + 1;
+          parts += (glen + part - 1) / part;
+          rows += (glen + part - 1) / part + 1;
           sparts += (gs + kPart - 1) / kPart;
           srows += (gs + kPart - 1) / kPart + 1;
         }
@@ -2489,7 +2490,8 @@ hipError_t launch_tile_sort(int kt, bool kv, const void *in, const uint32_t *vin
 
 hipError_t launch_seg_plan(const uint64_t *seg_off, uint32_t n_segs, uint64_t n,
                            const SegPlanPtrs &pp, uint32_t small0, uint32_t small1,
-                           uint32_t max_passes, uint32_t fan_log2, hipStream_t s) {
+                           uint32_t max_passes, uint32_t fan_log2, uint32_t tile, uint32_t part,
+                           hipStream_t s) {
   SegPlanArrays pa{};
   for (int c = 0; c < 3; ++c) pa.tiles[c] = pp.tiles[c];
   pa.soff = pp.soff;
@@ -2501,14 +2503,15 @@ hipError_t launch_seg_plan(const uint64_t *seg_off, uint32_t n_segs, uint64_t n,
     pa.sparts[q] = pp.sparts[q];
   }
   hipLaunchKernelGGL(seg_plan_kernel, dim3(1), dim3(1024), 0, s, seg_off, n_segs, n, pa, small0,
-                     small1, max_passes, fan_log2);
+                     small1, max_passes, fan_log2, tile, part);
   return hipGetLastError();
 }
 
 hipError_t launch_seg_tile_sorts(int kt, bool kv, const void *in, const uint32_t *vin, void *out,
                                  void *out_alt, uint32_t *vout, uint32_t *vout_alt, void *samples,
                                  const uint64_t *seg_off, const SegPlanPtrs &pp, uint32_t n_segs,
-                                 uint64_t n, hipStream_t s) {
+                                 uint64_t n, uint32_t tile, hipStream_t s) {
+  if (tile != (uint32_t)kTile && !(kv && tile == (uint32_t)kTileKV)) return hipErrorInvalidValue;
   return dispatch_kt(kt, [&](auto ktc) {
     constexpr int KT = decltype(ktc)::value;
     using U = typename Key<KT>::U;
@@ -2524,7 +2527,7 @@ hipError_t launch_seg_tile_sorts(int kt, bool kv, const void *in, const uint32_t
     ta.n_segs = n_segs;
     hipError_t e;
     // class 0: one 2048-key tile per segment; class 1: one 4096-key tile;
-    // class 2: tiles of kTile keys
+    // class 2: tiles of `tile` keys
     ta.tiles = pp.tiles[0];
     e = kv ? go_tile<KT, true, kSmallThreads0>(in, vin, ta, n_segs, s)
            : go_tile<KT, false, kSmallThreads0>(in, vin, ta, n_segs, s);
@@ -2534,7 +2537,8 @@ hipError_t launch_seg_tile_sorts(int kt, bool kv, const void *in, const uint32_t
            : go_tile<KT, false, kSmallThreads1>(in, vin, ta, n_segs, s);
     if (e != hipSuccess) return e;
     ta.tiles = pp.tiles[2];
-    const uint64_t grid = (n + kTile - 1) / kTile + n_segs;
+    const uint64_t grid = (n + tile - 1) / tile + n_segs;
+    if (kv && tile == (uint32_t)kTileKV) return go_tile<KT, true, kTileKVThreads>(in, vin, ta, grid, s);
     return kv ? go_tile<KT, true, kTileThreads>(in, vin, ta, grid, s)
               : go_tile<KT, false, kTileThreads>(in, vin, ta, grid, s);
   });
@@ -2681,8 +2685,8 @@ hipError_t launch_merge(int kt, int vmode, const void *src, const uint32_t *vsrc
     };
     const bool kv = vmode == 1;
     if (g.part_len != (uint32_t)kPart) {
-      // key-value passes of the automatic plan: 4096-key partitions
-      if (!kv || g.part_len != (uint32_t)kPartKV || g.fan > 64 || g.seg.off || g.paper)
+      // key-value passes of the automatic plan and segmented mode: 4096-key partitions
+      if (!kv || g.part_len != (uint32_t)kPartKV || g.fan > 64 || g.paper)
         return hipErrorInvalidValue;
       constexpr uint32_t NT = 2 * kMergeThreads;
       hipLaunchKernelGGL((merge_kernel<KT, 1, 64, NT, kPartKV>), dim3((uint32_t)parts), dim3(NT), 0,

@@ -15,10 +15,12 @@ hipError_t read_device_error_async(uint32_t *, hipStream_t) { return none(); }
 hipError_t launch_tile_sort(int, bool, const void *, const uint32_t *, void *, uint32_t *, uint64_t,
                             uint64_t, uint32_t, int, void *, hipStream_t) { return none(); }
 hipError_t launch_seg_plan(const uint64_t *, uint32_t, uint64_t, const SegPlanPtrs &, uint32_t,
-                           uint32_t, uint32_t, uint32_t, hipStream_t) { return none(); }
+                           uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, hipStream_t) {
+  return none();
+}
 hipError_t launch_seg_tile_sorts(int, bool, const void *, const uint32_t *, void *, void *,
                                  uint32_t *, uint32_t *, void *, const uint64_t *,
-                                 const SegPlanPtrs &, uint32_t, uint64_t, hipStream_t) {
+                                 const SegPlanPtrs &, uint32_t, uint64_t, uint32_t, hipStream_t) {
   return none();
 }
 hipError_t launch_corank(int, const void *, const RunGeom &, uint32_t *, void *, uint64_t *,

@@ -181,13 +181,15 @@ def test_segmented_full_batch_4096_segments():
 @pytest.mark.parametrize("fan", [5, 6], ids=["fan32", "fan64"])
 @pytest.mark.parametrize("kv", [False, True], ids=["keys", "key-value"])
 def test_segmented_three_merge_passes(kv, fan):
-    """Segments above 2^23 keys take three merge passes of 32 runs (2^11+
-    tiles of 8192 keys) with the segment's data ending in the output or the
-    workspace by the parity of its own pass count: segments of 2^23 + 1 and
-    2^24 keys (three passes), 2^23 (two), 2^20 + 3 (two) and short ones (none
-    or one), mixed, against the oracle segment by segment.  With 64 runs per
-    pass the same segments take two passes (2^24: 2048 tiles = 64 x 32) and
-    2^20 + 3 one pass fewer, so the parities differ."""
+    """Keys only, segments above 2^23 keys take three merge passes of 32 runs
+    (2^11+ tiles of 8192 keys) with the segment's data ending in the output or
+    the workspace by the parity of its own pass count: segments of 2^23 + 1
+    and 2^24 keys (three passes), 2^23 (two), 2^20 + 3 (two) and short ones
+    (none or one), mixed, against the oracle segment by segment.  With 64
+    runs per pass the same segments take two passes (2^24: 2048 tiles =
+    64 x 32) and 2^20 + 3 one pass fewer, so the parities differ.  Key-value
+    batches use 4096-key tiles: 2^23 + 1 and 2^24 keys take three passes of
+    32 runs and two of 64, 2^20 + 3 two passes either way."""
     sizes = np.array([1000, (1 << 23) + 1, 5, (1 << 20) + 3, 1 << 24, 8193, 1 << 23, 0, 77],
                      dtype=np.int64)
     offs = np.zeros(sizes.size + 1, dtype=np.int64)

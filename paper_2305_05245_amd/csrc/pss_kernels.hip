@@ -2613,17 +2613,7 @@ hipError_t launch_corank_sampled(int kt, const void *src, const RunGeom &g, uint
   using E2 = std::integral_constant<int, 2>;
   using E4 = std::integral_constant<int, 4>;
   const bool wide = key_bytes(kt) == 8;
-  // 33-64 runs outside segmented mode: up to 192 candidates a level, for
-  // which radix selection of the two bracket ranks beats the four-slot
-  // bitonic network (measured on the key-value plan's 64-run pass)
-  auto radix64 = [&](auto u) -> hipError_t {
-    using U = decltype(u);
-    hipLaunchKernelGGL((corank_kernel<U, 64, 4, true>), dim3((uint32_t)rows), dim3(kCorankThreads),
-                       0, s, (const U *)src, g, table, (U *)nullptr, (uint64_t *)nullptr, kt, si);
-    return hipGetLastError();
-  };
   if (g.fan <= 32) return wide ? wave(uint64_t{}, E2{}) : wave(uint32_t{}, E2{});
-  if (g.fan <= 64 && !g.seg.off) return wide ? radix64(uint64_t{}) : radix64(uint32_t{});
   if (g.fan <= 64) return wide ? wave(uint64_t{}, E4{}) : wave(uint32_t{}, E4{});
   // 65-256 runs (the paper's single level only): per-run counts in LDS
   if (g.seg.off) return hipErrorInvalidValue;

@@ -460,8 +460,8 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
   for (int i = 0; i < kTileItems; ++i) {
     const uint32_t idx = i * THREADS + tid;
     const uint32_t j = idx < len ? idx : len - 1;  // len >= 1 for every tile launched
-    raw[i] = in[start + j];
-    if constexpr (KV) vraw[i] = vin[start + j];
+    raw[i] = __builtin_nontemporal_load(&in[start + j]);  // read once
+    if constexpr (KV) vraw[i] = __builtin_nontemporal_load(&vin[start + j]);
   }
 #pragma unroll
   for (int i = 0; i < kTileItems; ++i) {
@@ -629,8 +629,10 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
     const uint32_t idx = i * THREADS + tid;
     if (idx < len) {
       const U k = sk[idx];
-      out[start + idx] = final_pass ? Key<KT>::unmap(k) : k;
-      if constexpr (KV) vout[start + idx] = sv[idx];
+      // written once and read a pass later: non-temporal, so that the
+      // samples the next pass reads soon stay in L2
+      __builtin_nontemporal_store(final_pass ? Key<KT>::unmap(k) : k, &out[start + idx]);
+      if constexpr (KV) __builtin_nontemporal_store(sv[idx], &vout[start + idx]);
     }
   }
   // regular samples of the sorted tile (every kSample-th key, tile positions
@@ -1788,8 +1790,8 @@ void merge_kernel(
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const uint32_t idx = i * NT + tid;
-      kreg[i] = idx < M ? src[addr[i]] : U(0);
-      if constexpr (VMODE == 1) vreg[i] = idx < M ? vsrc[addr[i]] : 0u;
+      kreg[i] = idx < M ? __builtin_nontemporal_load(&src[addr[i]]) : U(0);  // read once
+      if constexpr (VMODE == 1) vreg[i] = idx < M ? __builtin_nontemporal_load(&vsrc[addr[i]]) : 0u;
       if constexpr (VMODE == 2) vreg[i] = runid[i];
     }
     if constexpr (MAXF <= 64) {
@@ -1989,8 +1991,8 @@ void merge_kernel(
     const uint32_t idx = i * NT + tid;
     if (idx < M) {
       const U k = sk[idx];
-      dst[pi.out_off + idx] = final_pass ? Key<KT>::unmap(k) : k;
-      if constexpr (KV) vdst[pi.out_off + idx] = sv[idx];
+      __builtin_nontemporal_store(final_pass ? Key<KT>::unmap(k) : k, &dst[pi.out_off + idx]);
+      if constexpr (KV) __builtin_nontemporal_store(sv[idx], &vdst[pi.out_off + idx]);
     }
   }
   if (write_samples && !g.paper) {

@@ -20,7 +20,7 @@ import torch
 from . import _lib
 from ._lib import PssError, Tuning, plan, validate, workspace_bytes  # noqa: F401
 
-__all__ = ["sort", "segmented_sort", "splitters", "psrs_sort", "psrs_splitters", "sort_records", "set_merge_method", "device_check", "Tuning", "key_type_of", "plan", "workspace_bytes", "PssError",
+__all__ = ["sort", "sort_noalloc", "segmented_sort", "splitters", "psrs_sort", "psrs_splitters", "sort_records", "set_merge_method", "device_check", "Tuning", "key_type_of", "plan", "workspace_bytes", "PssError",
            "Workspace"]
 
 _DTYPE_KEY = {
@@ -118,6 +118,40 @@ def sort(keys: torch.Tensor, vals: torch.Tensor | None = None, n_blocks: int = 0
              vals.data_ptr() if vals is not None else 0,
              vals_out.data_ptr() if vals is not None else 0,
              n, n_blocks, n_parts, ws.data_ptr(), ws.numel(), _stream_handle(dev))
+    return out, (vals_out if vals is not None else None)
+
+
+def sort_noalloc(keys: torch.Tensor, out: torch.Tensor, vals: torch.Tensor | None = None,
+                 vals_out: torch.Tensor | None = None, n_blocks: int = 0, n_parts: int = 0,
+                 key_type: str | int | None = None):
+    """`sort` on the library's fixed scratch array instead of a workspace: the
+    call allocates no device memory (for graph capture and loops that must not
+    allocate), so the caller passes the outputs.  Sorts whose workspace would
+    exceed NOALLOC_SCRATCH_BYTES (64 MiB) raise PssError (ERR_WORKSPACE).
+    Calls that overlap on one device share the array and must not run
+    concurrently."""
+    if not keys.is_cuda or keys.dim() != 1 or not keys.is_contiguous():
+        raise ValueError("keys must be a contiguous 1-D device tensor")
+    kt = key_type_of(keys, key_type)
+    if keys.element_size() != _lib.KEY_BYTES[kt]:
+        raise ValueError("key dtype width does not match key_type")
+    if out is None or out.shape != keys.shape or out.dtype != keys.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous tensor shaped like keys")
+    n = keys.numel()
+    vt = _lib.VAL_NONE
+    if vals is not None:
+        if (not vals.is_cuda or vals.numel() != n or vals.element_size() != 4
+                or not vals.is_contiguous()):
+            raise ValueError("vals must be a contiguous device tensor of n 4-byte elements")
+        if (vals_out is None or vals_out.numel() != n or vals_out.element_size() != 4
+                or not vals_out.is_contiguous()):
+            raise ValueError("vals_out must be a contiguous tensor of n 4-byte elements")
+        vt = _lib.VAL_U32
+    dev = keys.device.index if keys.device.index is not None else torch.cuda.current_device()
+    _context(dev).sort_noalloc(kt, vt, keys.data_ptr(), out.data_ptr(),
+                               vals.data_ptr() if vals is not None else 0,
+                               vals_out.data_ptr() if vals is not None else 0,
+                               n, n_blocks, n_parts, _stream_handle(dev))
     return out, (vals_out if vals is not None else None)
 
 

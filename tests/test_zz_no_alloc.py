@@ -84,6 +84,27 @@ def test_noalloc_equals_pss_sort_two_calls(case):
     assert pss.device_check() == 0
 
 
+def test_noalloc_torch_wrapper_equals_sort():
+    """The torch-facing pss.sort_noalloc: caller-given outputs, the same
+    result as pss.sort, key-value included."""
+    import torch
+
+    import paper_2305_05245_amd as pss
+
+    n = 300_001
+    announce("noalloc torch wrapper", n)
+    dk = to_device(W.uniform_i64(n, seed=70))
+    dv = torch.arange(n, dtype=torch.int32, device="cuda")
+    ko, vo = torch.empty_like(dk), torch.empty_like(dv)
+    pss.sort_noalloc(dk, ko, dv, vo)
+    ek, ev = pss.sort(dk, dv)
+    torch.cuda.synchronize()
+    assert torch.equal(ko, ek) and torch.equal(vo, ev)
+    with pytest.raises(ValueError):
+        pss.sort_noalloc(dk, None)
+    assert pss.device_check() == 0
+
+
 def test_noalloc_refuses_requests_above_the_scratch_array():
     import torch
 

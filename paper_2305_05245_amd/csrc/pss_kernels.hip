@@ -463,21 +463,32 @@ __global__ __launch_bounds__(THREADS) void tile_sort_kernel(
     raw[i] = __builtin_nontemporal_load(&in[start + j]);  // read once
     if constexpr (KV) vraw[i] = __builtin_nontemporal_load(&vin[start + j]);
   }
-#pragma unroll
-  for (int i = 0; i < kTileItems; ++i) {
-    const uint32_t idx = i * THREADS + tid;
-    sk[tile_pad(idx)] = idx < len ? Key<KT>::map(raw[i]) : key_max<U>();
-    if constexpr (KV) sv[pad16(idx)] = idx < len ? vraw[i] : 0u;
-  }
-  __syncthreads();
-
   U rk[kTileItems];
   uint32_t rv[KV ? kTileItems : 1];
+  if constexpr (KV) {
+    // A stable sort needs each thread's keys to be consecutive in the input:
+    // through LDS, from the coalesced load order to 16 consecutive keys.
 #pragma unroll
-  for (int i = 0; i < kTileItems; ++i) {
-    const uint32_t idx = tid * kTileItems + i;
-    rk[i] = sk[tile_pad(idx)];
-    if constexpr (KV) rv[i] = sv[pad16(idx)];
+    for (int i = 0; i < kTileItems; ++i) {
+      const uint32_t idx = i * THREADS + tid;
+      sk[tile_pad(idx)] = idx < len ? Key<KT>::map(raw[i]) : key_max<U>();
+      sv[pad16(idx)] = idx < len ? vraw[i] : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kTileItems; ++i) {
+      const uint32_t idx = tid * kTileItems + i;
+      rk[i] = sk[tile_pad(idx)];
+      rv[i] = sv[pad16(idx)];
+    }
+  } else {
+    // Keys only: which 16 keys of the tile a thread sorts does not matter,
+    // so it sorts the ones it loaded (tile positions i * THREADS + tid).
+#pragma unroll
+    for (int i = 0; i < kTileItems; ++i) {
+      const uint32_t idx = i * THREADS + tid;
+      rk[i] = idx < len ? Key<KT>::map(raw[i]) : key_max<U>();
+    }
   }
   register_sort<U, KV, kTileItems>(rk, rv);
   if constexpr (KV) {

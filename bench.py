@@ -4,7 +4,7 @@ One step = one complete sort (every step of the method: tile sort, splitter
 search, partitioning, multiway merges) of N = 2^28 int64 keys already resident
 in HBM, into a separate output array.  Prints ONE JSON line.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--dist uniform]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--dist uniform]
                     [--log2n 28] [--all-dists] [--no-cpu-baseline]
                     [--no-batched] [--no-serving] [--leg batched|serving]
 
@@ -759,7 +759,7 @@ def bench_serving(torch, _unused: float, n_req: int = 20000, warm_req: int = 200
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--dist", default="uniform", choices=list(generators()))

@@ -113,7 +113,10 @@ pss_status pss_workspace_bytes(const pss_ctx *ctx, pss_key_t key, pss_val_t val,
  *   {"mode": "auto"|"paper", "tile": T, "part": T_m, "passes": [fan-in, ...],
  *    "block_passes": [...], "n_blocks": n_B, "n_parts": n_P, "hbm_passes": h}
  * where "passes" are the merge passes after the tile sort and "hbm_passes"
- * the number of full read+write sweeps over the keys.  Host-only. */
+ * the number of full read+write sweeps over the keys.  Keys-only sorts use
+ * tiles and merge partitions of 8192 keys and passes of at most 32 runs;
+ * key-value sorts tiles and partitions of 4096 keys and passes of at most 64
+ * runs (they hold 12 bytes a key in LDS).  Host-only. */
 pss_status pss_plan_describe(pss_key_t key, pss_val_t val, uint64_t n, uint32_t n_blocks,
                              uint32_t n_parts, char *buf, size_t buf_len);
 
@@ -252,8 +255,9 @@ pss_status pss_sort_records(pss_ctx *ctx, pss_key_t key, const void *records_in,
  * segment), all segments in one fixed sequence of launches with no host round
  * trip, so the sequence can be captured once into a hipGraph and replayed.
  * The segments' shapes are read on the device: a planning kernel classifies
- * every segment (one small tile, or tiles of 8192 keys plus merge passes of
- * fan-in 32 or 64 with exact splitting, the paper's steps 2-4 applied per segment),
+ * every segment (one small tile, or tiles of 8192 keys (4096 with values) plus
+ * merge passes of fan-in 32 or 64 with exact splitting, the paper's steps 2-4
+ * applied per segment),
  * and every later kernel finds its segment through the plan's prefix tables.
  *
  *   seg_offsets: DEVICE array of n_segs + 1 uint64, seg_offsets[0] = 0,

@@ -92,7 +92,7 @@ def test_workspace_bytes_grow_with_n(lib):
 
 @pytest.mark.parametrize("n,passes", [
     (1, []), (8192, []), (8193, [2]), (1 << 20, [16, 8]),
-    (1 << 28, [32, 32, 32]), (1 << 27, [32, 32, 16]),
+    (1 << 28, [32, 32, 32]), (1 << 27, [32, 32, 16]), ((1 << 28) + 3, [16, 16, 16, 16]),
 ])
 def test_auto_plan(lib, n, passes):
     p = _lib.plan(_lib.I64, 0, n)

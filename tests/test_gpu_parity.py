@@ -125,6 +125,17 @@ def test_key_value_fan64_passes():
             assert same_bits(gk, ek) and np.array_equal(gv, ev), (kind, n)
 
 
+def test_four_merge_passes():
+    """2^28 + 3 int64 keys: 2^15 + 1 tiles, so the plan takes four merge
+    passes of 16 runs (and the tile sort's output starts in the workspace).
+    int64 keys sort uniquely: the output must equal numpy's sort."""
+    n = (1 << 28) + 3
+    keys = W.uniform_i64(n, seed=21)
+    announce("auto-4-pass", n)
+    got, _ = gpu_sort(keys)
+    assert np.array_equal(got, np.sort(keys))
+
+
 def test_medium_sizes_three_passes():
     # 2^24 keys: 2048 tiles, three merge passes
     keys = W.uniform_i64(1 << 24, seed=2)

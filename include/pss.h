@@ -432,6 +432,12 @@ pss_status pss_set_merge_method(pss_ctx *ctx, pss_merge_method method);
 pss_status pss_profile_enable(pss_ctx *ctx, int on);
 pss_status pss_profile_read(pss_ctx *ctx, char *buf, size_t buf_len);
 
+/* Restrict the per-launch timing to one kernel family (a name from the list
+ * above, copied; NULL or "" = every launch), so that a measurement of one
+ * kernel adds events around its launches only.  Returns PSS_ERR_INVALID for
+ * a null ctx or a name longer than 63 characters. */
+pss_status pss_profile_only(pss_ctx *ctx, const char *family);
+
 /*
  * Wait for all work on ctx's device, then read and clear the library's device
  * error word into *code (host memory): 0 when every kernel found its

@@ -155,9 +155,12 @@ def sort_noalloc(keys: torch.Tensor, out: torch.Tensor, vals: torch.Tensor | Non
     return out, (vals_out if vals is not None else None)
 
 
-def profile(on: bool, device: int = 0) -> None:
-    """Turn per-launch event timing of the library on or off."""
-    _context(device).profile(on)
+def profile(on: bool, device: int = 0, only: str | None = None) -> None:
+    """Turn per-launch event timing of the library on or off; `only` limits
+    it to one kernel family (e.g. "merge"), None times every launch."""
+    ctx = _context(device)
+    ctx.profile_only(only)
+    ctx.profile(on)
 
 
 def profile_read(device: int = 0) -> dict:

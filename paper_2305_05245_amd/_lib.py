@@ -75,6 +75,7 @@ SIGNATURES = {
                                   _sz, _vp]),
     "pss_profile_enable": (_int, [_vp, _int]),
     "pss_profile_read": (_int, [_vp, _c.c_char_p, _sz]),
+    "pss_profile_only": (_int, [_vp, _c.c_char_p]),
     "pss_server_create": (_int, [_vp, _sz, _u32, _vp, _c.POINTER(_vp)]),
     "pss_submit": (_int, [_vp, _c.POINTER(Request), _c.POINTER(_u64)]),
     "pss_poll": (_int, [_vp, _u64, _c.POINTER(_int), _c.POINTER(_int)]),
@@ -283,6 +284,10 @@ class Context:
 
     def profile(self, on: bool) -> None:
         self._call("pss_profile_enable", 1 if on else 0)
+
+    def profile_only(self, family: str | None) -> None:
+        """Time only this kernel family's launches while profiling (None: all)."""
+        self._call("pss_profile_only", family.encode() if family else None)
 
     def profile_read(self) -> dict:
         buf = ctypes.create_string_buffer(1 << 16)

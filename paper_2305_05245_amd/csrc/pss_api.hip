@@ -22,6 +22,7 @@ struct pss_ctx {
   int device = 0;
   std::string last_error;
   bool profiling = false;
+  std::string profile_only;  // kernel family timed while profiling ("" = all)
   pss_merge_method merge_method = PSS_MERGE_PAIRWISE;
   std::vector<pss_prof_rec> recs;
   std::vector<hipEvent_t> pool;  // events ready for reuse
@@ -267,8 +268,9 @@ pss_status validate(const pss_ctx *ctx, pss_key_t key, pss_val_t val, const void
     PSS_TRY(expr, what);                                                               \
   } while (0)
 
-// Optional per-launch timing: when profiling is on, every kernel launch is
-// bracketed by two events recorded on the launch stream.
+// Optional per-launch timing: when profiling is on, every kernel launch (or
+// every launch of the family chosen by pss_profile_only) is bracketed by two
+// events recorded on the launch stream.
 hipEvent_t take_event(pss_ctx *ctx) {
   if (!ctx->pool.empty()) {
     hipEvent_t e = ctx->pool.back();
@@ -286,7 +288,8 @@ struct LaunchTimer {
   pss_prof_rec rec{};
   bool on;
   LaunchTimer(pss_ctx *c, const char *name, uint64_t bytes, hipStream_t st)
-      : ctx(c), s(st), on(c && c->profiling) {
+      : ctx(c), s(st),
+        on(c && c->profiling && (c->profile_only.empty() || c->profile_only == name)) {
     if (!on) return;
     rec.name = name;
     rec.bytes = bytes;
@@ -735,6 +738,13 @@ pss_status pss_set_merge_method(pss_ctx *ctx, pss_merge_method method) {
 pss_status pss_profile_enable(pss_ctx *ctx, int on) {
   if (!ctx) return fail(nullptr, PSS_ERR_INVALID, "null context");
   ctx->profiling = on != 0;
+  return PSS_OK;
+}
+
+pss_status pss_profile_only(pss_ctx *ctx, const char *family) {
+  if (!ctx) return fail(nullptr, PSS_ERR_INVALID, "null context");
+  if (family && strnlen(family, 64) > 63) return fail(ctx, PSS_ERR_INVALID, "family name too long");
+  ctx->profile_only = family ? family : "";
   return PSS_OK;
 }
 

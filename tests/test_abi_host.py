@@ -166,3 +166,8 @@ def test_tuning_struct_and_fan_choice(lib):
     assert e.value.status == _lib.ERR_INVALID
     d = _lib.Tuning.from_dict({"small_max_2k": 512, "fan_log2": 6}).as_dict()
     assert d["small_max_2k"] == 512 and d["small_max_4k"] == 4096 and d["fan_log2"] == 6
+
+
+def test_profile_only_rejects_null_context_and_long_names(lib):
+    assert lib.pss_profile_only(None, b"merge") == _lib.ERR_INVALID
+    assert lib.pss_profile_only(None, None) == _lib.ERR_INVALID

@@ -101,7 +101,8 @@ def test_auto_sort_structured(dtype, kind):
                          ids=lambda d: np.dtype(d).name)
 @pytest.mark.parametrize("kind", ["uniform", "dup"])
 def test_auto_key_value_stable(dtype, kind):
-    for n in (1, 5000, 8192, 70001, 600000):
+    # 4095 / 4096 / 4097 / 12289: edges of the 4096-key tiles key-value sorts use
+    for n in (1, 4095, 4096, 4097, 5000, 8192, 12289, 70001, 600000):
         keys = seeded_keys(dtype, n, 31, kind)
         vals = np.arange(n, dtype=np.uint32)
         announce("auto-kv", np.dtype(dtype).name, kind, n)

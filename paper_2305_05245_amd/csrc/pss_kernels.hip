@@ -374,11 +374,12 @@ __device__ __forceinline__ void lane_runs_to_128(U (&k)[kTileItems], uint32_t la
 }
 
 // --------------------------------------------------------------- K1 -------
-// One workgroup sorts one tile of at most kTile keys of one segment.  Keys are
-// mapped on load (K0), each thread sorts 16 consecutive keys in registers, then
-// log2(kTile/16) rounds of stable merge-path merges run through LDS.  A short
-// tile is padded with the largest key; pads sit after every real key (for
-// key-value sorts the network and merges are stable, so pads stay last).
+// One workgroup sorts one tile of THREADS * 16 keys of one segment.  Keys
+// are mapped on load (K0) and each thread sorts 16 of them in registers (the
+// ones it loaded for keys only, 16 consecutive ones for key-value tiles); then
+// runs are merged, across lanes and through LDS, up to the whole tile.  A
+// short tile is padded with the largest key; pads sit after every real key
+// (for key-value sorts the network and merges are stable, so pads stay last).
 // Where one tile-sort workgroup reads and writes.  Uniform mode: tiles of
 // kTile keys in uniform segments.  Segmented mode: `tiles` is the prefix over
 // segments of the tiles of this launch's tile size (0 for segments another

@@ -543,16 +543,53 @@ def bench_batched(pss, torch, steps: int, warmup: int) -> dict:
     t_each = (time.perf_counter() - t0) / reps
     same = bool(torch.equal(out, out2))
     graph.close()
+    del out2, sws
+
+    # the same batch as u64 keys with their uint32 input index as value (the
+    # serving loop's record), replayed from one captured graph
+    vals = torch.arange(total, dtype=torch.int32, device="cuda")
+    vout = torch.empty_like(vals)
+    kv_best = autotune.cached(_lib.U64, _lib.VAL_U32, total, n_segs)
+    kv_source = "cache"
+    if kv_best is None:
+        kv_best = autotune.tune(_lib.U64, _lib.VAL_U32, total, n_segs, reps=2, store=False)
+        kv_source = "tuned now"
+    kv_tu = _lib.Tuning(int(kv_best["small_max_2k"]), int(kv_best["small_max_4k"]),
+                        int(sizes.max()), int(kv_best.get("fan_log2", 5)), 0)
+    kws = torch.empty(_lib.segmented_workspace_bytes(_lib.U64, _lib.VAL_U32, total, n_segs, kv_tu),
+                      dtype=torch.uint8, device="cuda")
+    kv_graph = ctx.segmented_graph(_lib.U64, _lib.VAL_U32, keys.data_ptr(), out.data_ptr(),
+                                   vals.data_ptr(), vout.data_ptr(), total, d_offs.data_ptr(),
+                                   n_segs, kv_tu, kws.data_ptr(), kws.numel())
+    for _ in range(warmup):
+        kv_graph.launch(h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        kv_graph.launch(h)
+    torch.cuda.synchronize()
+    t_kv = (time.perf_counter() - t0) / steps
+    kv_graph.close()
+    # every value must carry its own key (the parity tests check the order)
+    kv_consistent = bool(torch.equal(keys[vout.long()], out))
+    del kws, vals, vout
     assert pss.device_check(0) == 0
     return {"workload": "4096 int64 arrays, sizes round(2^U), U~Uniform[6,20] (seed 12), "
                         "uniform keys (seed 13)",
+            "key_value": {"workload": "the same batch as u64 keys + u32 index values, stable",
+                          "graph_ms": round(t_kv * 1e3, 3),
+                          "graph_gkeys_per_s": round(total / t_kv / 1e9, 3),
+                          "tuning": {"small_max_2k": kv_tu.small_max_2k,
+                                     "small_max_4k": kv_tu.small_max_4k,
+                                     "fan_log2": kv_tu.fan_log2 or 5, "source": kv_source},
+                          "values_carry_their_keys": kv_consistent},
             "total_keys": total, "graph_ms": round(t_graph * 1e3, 3),
             "graph_gkeys_per_s": round(total / t_graph / 1e9, 3),
             "per_array_ms": round(t_each * 1e3, 3),
             "per_array_gkeys_per_s": round(total / t_each / 1e9, 3),
             "speedup_vs_per_array": round(t_each / t_graph, 2),
             "tuning": {"small_max_2k": tu.small_max_2k, "small_max_4k": tu.small_max_4k,
-                       "source": source},
+                       "fan_log2": tu.fan_log2 or 5, "source": source},
             "outputs_identical": same}
 
 

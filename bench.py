@@ -141,15 +141,32 @@ def cpu_child(mode: str, log2n: int) -> int:
     loops over blocks, pivots and partitions on T OpenMP threads (T as the
     OpenMP runtime sets it: OMP_NUM_THREADS where the environment gives the
     process its share of the host, else every core), n_B = n_P = T as in the
-    paper's setting, mean of 3 runs."""
+    paper's setting, mean of 3 runs.  mode "oracle_small": the sequential
+    oracle on the small case (2^20 int32, seed 1, n_B = n_P = 64), pinned,
+    mean of 5 runs."""
     import numpy as np
 
     import oracle
     import workloads as W
 
     cores = sorted(os.sched_getaffinity(0))
-    if mode == "oracle":
+    if mode in ("oracle", "oracle_small"):
         os.sched_setaffinity(0, {cores[0]})
+    if mode == "oracle_small":
+        # the paper-sized small case: 2^20 int32 (seed 1), the paper's single
+        # level with n_B = n_P = 64, five runs on one pinned core
+        n = 1 << 20
+        keys = W.uniform_i32(n, seed=1)
+        oracle.build()
+        runs = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            out = oracle.pses(keys, 64, 64).keys
+            runs.append(time.perf_counter() - t0)
+        res = {"n": n, "seconds": float(np.mean(runs)), "cores": 1, "core": cores[0], "runs": 5,
+               "ascending": bool(np.all(out[1:] >= out[:-1]))}
+        print(json.dumps(res), flush=True)
+        return 0
     n = 1 << log2n
     keys = W.uniform_i64(n, seed=2)
     res = {"n": n, "cpu_model": _cpu_model()}
@@ -190,8 +207,9 @@ def cpu_baseline(log2n: int = CPU_BASELINE_LOG2N) -> dict:
 
     seq = child("oracle")
     par = child("host")
+    small = child("oracle_small")
     n = seq["n"]
-    assert seq["ascending"] and par["ascending"]
+    assert seq["ascending"] and par["ascending"] and small["ascending"]
     return {"value": n / seq["seconds"] / 1e9, "unit": "GKeys/s", "cores": 1, "kind": "oracle",
             "sample": f"the full 2^{log2n} uniform int64 keys (seed 2) of the single-sort "
                       f"workload, sequential oracle, n_B = n_P = 16, pinned to core "
@@ -201,7 +219,12 @@ def cpu_baseline(log2n: int = CPU_BASELINE_LOG2N) -> dict:
                 "value": n / par["seconds"] / 1e9, "unit": "GKeys/s", "cores": par["cores"],
                 "kind": "oracle steps 1-4 with their loops over blocks, pivots and partitions "
                         "on OpenMP threads, n_B = n_P = threads",
-                "seconds_mean_of_3": round(par["seconds"], 3), "run_seconds": par["run_seconds"]}}
+                "seconds_mean_of_3": round(par["seconds"], 3), "run_seconds": par["run_seconds"]},
+            "small_case": {
+                "value": small["n"] / small["seconds"] / 1e9, "unit": "GKeys/s", "cores": 1,
+                "kind": "oracle", "sample": "2^20 uniform int32 keys (seed 1), the paper's single "
+                                            "level with n_B = n_P = 64, pinned to one core",
+                "seconds_mean_of_5": round(small["seconds"], 4)}}
 
 
 def bench_key_value(pss, torch, log2n: int, steps: int, warmup: int) -> dict:
@@ -820,7 +843,7 @@ def main() -> int:
     ap.add_argument("--leg", choices=("batched", "serving", "key_value", "splitting", "records",
                                       "paper_inputs", "distributions"),
                     help="run only this leg and print its JSON object (for profiling)")
-    ap.add_argument("--cpu-child", choices=("oracle", "host"), help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-child", choices=("oracle", "host", "oracle_small"), help=argparse.SUPPRESS)
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a plain device-to-device copy of the keys (bandwidth and "
                          "counter calibration), print its line and exit")

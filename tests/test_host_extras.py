@@ -73,3 +73,26 @@ def test_kernel_source_digest_ignores_comments(tmp_path):
     c.write_text("int f(int x) {\n  return x + 2;\n}\n")
     assert bench.kernel_source_digest(str(a)) == bench.kernel_source_digest(str(b))
     assert bench.kernel_source_digest(str(a)) != bench.kernel_source_digest(str(c))
+
+
+def test_measured_traffic_is_read_only_for_the_source_it_was_taken_on():
+    """bench.py reads the merge kernel's HBM traffic from the committed counter
+    summary only while its source digest matches the kernel source; when it
+    does, the figure lies between the algorithmic bytes and twice them."""
+    import bench
+
+    t = bench.measured_traffic("merge", 28, "uniform")
+    if t is not None:
+        assert 16 * (1 << 28) <= t <= 32 * (1 << 28)
+    assert bench.measured_traffic("tile_sort", 28, "uniform") is None
+    assert bench.measured_traffic("merge", 27, "uniform") is None
+
+
+def test_small_case_cpu_child_prints_one_json_object():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--cpu-child", "oracle_small"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    import json
+
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    assert res["n"] == 1 << 20 and res["runs"] == 5 and res["ascending"] and res["seconds"] > 0
